@@ -1,0 +1,50 @@
+"""Statistics of per-cell fields and the energy spectrum (oracle side).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+"""
+import numpy as np
+
+
+def field_stats(v):
+    """Two-pass FP64 statistics of a field: n, mean, var, skewness, flatness, min, max.
+
+    var is the population variance <(v - <v>)^2>; skewness <d^3>/var^1.5 and
+    flatness <d^4>/var^2 (NaN when var == 0).  These are the domain statistics
+    of tau_e - 1/2 and K_t the paper reports (Sec. 5.1).
+    """
+    v = np.asarray(v, dtype=np.float64).ravel()
+    n = v.size
+    mean = v.sum() / n
+    d = v - mean
+    var = (d * d).sum() / n
+    if var > 0:
+        skew = (d ** 3).sum() / n / var ** 1.5
+        flat = (d ** 4).sum() / n / var ** 2
+    else:
+        skew = float("nan")
+        flat = float("nan")
+    return dict(n=n, mean=mean, var=var, skew=skew, flat=flat, min=v.min(), max=v.max())
+
+
+def energy_spectrum(u):
+    """Shell-binned spectrum E(k), Sec. 2.2 eq. integral_length_scale.
+
+    Reading: the printed sum lacks the square; E(k) = 1/2 sum |u_hat(k)|^2 over
+    k - 1/2 <= |k| < k + 1/2, with u_hat = N^-3 sum_x u(x) exp(-i k.x), so that
+    sum_k E(k) = 1/2 <u.u> (Parseval).  u: (3, nz, ny, nx), integer wavenumbers.
+    Returns E for k = 0 .. kmax (kmax = the largest shell index present).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    _, nz, ny, nx = u.shape
+    n = nx * ny * nz
+    e = np.zeros((nz, ny, nx))
+    for a in range(3):
+        uh = np.fft.fftn(u[a]) / n
+        e += 0.5 * (uh.real ** 2 + uh.imag ** 2)
+    kz = np.fft.fftfreq(nz, 1.0 / nz)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    kx = np.fft.fftfreq(nx, 1.0 / nx)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    shell = np.floor(kmag + 0.5).astype(np.int64)
+    return np.bincount(shell.ravel(), weights=e.ravel())
