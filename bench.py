@@ -1,0 +1,254 @@
+#!/usr/bin/env python
+"""Benchmark of the D3Q19 MRT-Smagorinsky LES hot path on one MI355X.
+
+Prints ONE JSON line.  The headline workload is forced-HIT LES on a 100^3
+periodic lattice in FP32 with in-place AA streaming (Re = 2e4 at U0 = 0.043,
+C = 0.1, solenoidal forcing on |k| <= 2 with seeded phases, 1e-3 noise start,
+on-device K_t statistics every 500 steps).  A "step" is one lattice time step:
+the fused stream-and-collide kernel over every cell.  ``value`` is MLUPS
+(million lattice-cell updates per second) over the timed steps, with the
+state resident in HBM.
+
+Beside it the same line carries: the roofline of the step kernel (algorithmic
+bytes 2 * 19 * 4 per cell update over its average launch time, from HIP events
+on the kernel's stream), the 800^3 FP32 AA run, the batched-serving run
+(p50/p99 completion latency and aggregate MLUPS), and the FP64 C oracle timed
+on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, MRT-Smag 100^3/800^3; batched p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2512_23116_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_sha()
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 5 and not line.startswith("#") and parts[0] == workload_key \
+                and parts[1] == sha:
+            return float(parts[2]) + float(parts[3])
+    return None
+
+
+def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64):
+    import torch
+    stream = torch.cuda.Stream()
+    cfg = params.forced_hit(N)
+    lat = lbm.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"], precision=precision,
+                      streaming=streaming, steps_per_graph=spg, stream=stream)
+    lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
+    lat.step(warmup)
+    lat.sync()
+    stats = []
+    events = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(diag_every, steps - done) if diag_every else steps
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(n)
+        e1.record(stream)
+        events.append((e0, e1))
+        done += n
+        if diag_every and done % diag_every == 0:
+            stats.append(lat.stats())
+    lat.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
+    final = lat.stats()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ncell = N ** 3
+    bytes_per_launch = 2 * 19 * BYTES[precision] * ncell
+    avg = kern_s / steps
+    achieved = bytes_per_launch / avg / 1e9
+    return dict(N=N, steps=steps, wall_s=wall, mlups=ncell * steps / wall / 1e6,
+                ms_per_step=wall / steps * 1e3, avg_launch_us=avg * 1e6,
+                kernel_mlups=ncell / avg / 1e6,
+                roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=achieved / PEAK_HBM_GBS,
+                              bytes_per_launch=bytes_per_launch),
+                kt=dict(mean=final["kt_mean"], var=final["kt_var"], flat=final["kt_flat"],
+                        theta_mean=final["theta_mean"], n_snapshots=len(stats)),
+                tau0=cfg["tau0"])
+
+
+def cpu_baseline(N, target_s=12.0):
+    from oracle import init_fields as I
+    from oracle import ref_c
+    from paper_2512_23116_amd import params
+    cfg = params.forced_hit(N)
+    lat = ref_c.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"])
+    f = lat.init(I.KIND_NOISE, cfg["noise"], cfg["init_seed"])
+    t = time.perf_counter()
+    f = lat.step(f, 2)
+    probe = time.perf_counter() - t
+    n = max(2, min(200, int(target_s / max(probe / 2, 1e-6))))
+    t = time.perf_counter()
+    lat.step(f, n)
+    dt = time.perf_counter() - t
+    return dict(value=N ** 3 * n / dt / 1e6, unit="MLUPS", cores=ref_c.num_threads(),
+                kind="oracle",
+                sample=f"{N}^3 forced HIT, {n} steps of the plain C FP64 oracle (OpenMP)")
+
+
+def run_serving(n_req, steps, seed=2024):
+    from paper_2512_23116_amd import serving
+    # capacity: every request present at t = 0
+    reqs = serving.make_requests(n_req, seed=seed, steps=steps)
+    eng = serving.GpuEngine(max_slots=16, steps_per_graph=64)
+    closed = serving.serve(reqs, eng, max_slots=16, hbm_budget=80e9)
+    eng.close()
+    mean_updates = sum(r.cells * r.steps for r in reqs) / len(reqs)
+    rate = 0.8 * closed["busy_mlups"] * 1e6 / mean_updates
+    log(f"serving closed batch: {closed['busy_mlups']:.0f} MLUPS busy, "
+        f"{closed['wall_s']:.1f} s; Poisson rate {rate:.2f}/s")
+    reqs = serving.make_requests(n_req, seed=seed, steps=steps, rate=rate)
+    eng = serving.GpuEngine(max_slots=16, steps_per_graph=64)
+    res = serving.serve(reqs, eng, max_slots=16, hbm_budget=80e9)
+    eng.close()
+    return dict(requests=n_req, steps_each=steps, arrival_rate_per_s=rate,
+                p50_s=res["p50_s"], p99_s=res["p99_s"], aggregate_mlups=res["aggregate_mlups"],
+                busy_mlups=res["busy_mlups"], busy_frac=res["busy_frac"], failed=res["failed"],
+                capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--N", type=int, default=100)
+    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
+    ap.add_argument("--streaming", default="aa", choices=["aa", "ab"])
+    ap.add_argument("--diag-every", type=int, default=500)
+    ap.add_argument("--steps-per-graph", type=int, default=64)
+    ap.add_argument("--large-N", type=int, default=800)
+    ap.add_argument("--large-steps", type=int, default=1000)
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-steps", type=int, default=5000)
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the LES hot path here is single-device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_23116_amd import lbm, params
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    lbm.lib()
+
+    log(f"main: {args.N}^3 {args.precision} {args.streaming}, {args.steps} steps")
+    main_run = run_lattice(lbm, params, args.N, args.precision, args.streaming, args.steps,
+                           args.warmup, args.diag_every, args.steps_per_graph)
+    log(f"main: {main_run['mlups']:.0f} MLUPS, {main_run['avg_launch_us']:.1f} us/launch, "
+        f"{main_run['roofline']['frac']:.3f} of HBM peak")
+    key = f"{args.N}_{args.precision}_{args.streaming}"
+    main_run["roofline"]["traffic"] = counter_traffic(key)
+
+    large = None
+    if not args.no_large:
+        log(f"large: {args.large_N}^3 fp32 aa, {args.large_steps} steps")
+        large = run_lattice(lbm, params, args.large_N, "fp32", "aa", args.large_steps, 64,
+                            args.diag_every, args.steps_per_graph)
+        large["roofline"]["traffic"] = counter_traffic(f"{args.large_N}_fp32_aa")
+        log(f"large: {large['mlups']:.0f} MLUPS, {large['roofline']['frac']:.3f} of HBM peak")
+
+    serving = None
+    if not args.no_serving:
+        log(f"serving: {args.serving_requests} requests x {args.serving_steps} steps")
+        serving = run_serving(args.serving_requests, args.serving_steps)
+        log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s, "
+            f"{serving['aggregate_mlups']:.0f} MLUPS aggregate")
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: C oracle on the host cores")
+        cpu = cpu_baseline(args.N)
+        log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+
+    r = main_run["roofline"]
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64"}.get(args.precision, "f32"),
+        "data": "synthetic",
+        "config": {
+            "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C=0.1 "
+                         f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
+                         f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
+                         f"forcing, 1e-3 noise start, K_t stats every {args.diag_every} steps"),
+            "N": args.N, "precision": args.precision, "streaming": args.streaming,
+            "steps_per_graph": args.steps_per_graph, "parallelism": "single GPU",
+        },
+        "roofline": {"bound": r["bound"], "achieved": round(r["achieved"], 1), "peak": r["peak"],
+                     "unit": r["unit"], "frac": round(r["frac"], 4), "traffic": r["traffic"],
+                     "kernel": f"k_step {args.precision} {args.streaming}",
+                     "bytes_per_launch": r["bytes_per_launch"],
+                     "avg_launch_us": round(main_run["avg_launch_us"], 3)},
+        "cpu_baseline": cpu,
+        "kt": main_run["kt"],
+    }
+    if large:
+        lr = large["roofline"]
+        out["large"] = {"workload": f"forced HIT LES {args.large_N}^3 fp32 AA",
+                        "mlups": round(large["mlups"], 1), "steps": large["steps"],
+                        "ms_per_step": round(large["ms_per_step"], 4),
+                        "roofline": {"bound": "hbm", "achieved": round(lr["achieved"], 1),
+                                     "peak": lr["peak"], "unit": "GB/s",
+                                     "frac": round(lr["frac"], 4), "traffic": lr["traffic"]},
+                        "kt": large["kt"]}
+    if serving:
+        out["serving"] = serving
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * lbm.h — C-ABI of liblbm.so: the D3Q19 MRT-Smagorinsky LES update with Guo
+ * forcing on a periodic lattice, run by HIP kernels on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method (Khan, Succi & Falcucci, "Validating the Boltzmann approach to the
+ * large-eddy simulations of forced homogeneous incompressible turbulence",
+ * arXiv:2512.23116):
+ *   - lattice: D3Q19, App. B Fig. d3q19_table (velocities 0..18 here are the
+ *     paper's 1..19; opposite pairs (0,1),(2,3),...,(16,17); rest = 18);
+ *   - update: eq. mrt_les_guo (collide, then stream along c_a) with the
+ *     moment matrix of eq. moment-matrix, the rates of eq. relaxation-matrix,
+ *     the equilibrium and force moments of eq. meq_fm, the Guo velocity of
+ *     eq. guo_velocity;
+ *   - closure: per-cell tau_e = 1/2 + 3 (nu0 + C Delta^2 |S|)
+ *     (eq. nu_eff_mrt, eq. eddy_visc, eq. les_viscosity) with |S| of
+ *     eq. strain_norm from the strain of eq. yu_strain (s_1 = s_e, s_9 = 1/tau0,
+ *     Delta = delta_x = delta_t = 1);
+ *   - diagnostic: the turbulent Knudsen number K_t = sqrt(3) (tau_e - 1/2)
+ *     (eq. Kt_definition with ell = delta_x, Sec. 2.4).
+ *
+ * Conventions for every call
+ *   - Every entry point returns an lbm_status; no C++ exception crosses the
+ *     ABI.  lbm_last_error() gives a message for the last failing call on a
+ *     handle.
+ *   - Host pointers are plain host memory owned by the caller, with the sizes
+ *     stated per call; the library never keeps them after the call returns.
+ *   - Cell index c = x + nx (y + ny z), x fastest, 0-based coordinates.
+ *   - The observable state after n steps is the pre-collision, post-streaming
+ *     population field f(x, n) of eq. mrt_dns_guo.  It does not depend on the
+ *     streaming scheme or on the parity of n.
+ *   - All work is issued on the handle's HIP stream.  lbm_step returns before
+ *     the GPU finishes; kernel errors surface at the next synchronising call
+ *     (every call that writes host memory synchronises the stream).
+ *   - A handle is used from one host thread at a time.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID_ARG = -1,  /* bad config or argument; nothing was changed */
+    LBM_ERR_OUT_OF_MEMORY = -2,/* a device or host allocation failed          */
+    LBM_ERR_DEVICE = -3,       /* a HIP call or a kernel failed               */
+    LBM_ERR_UNSTABLE = -4,     /* the state holds NaN/Inf (reported by the
+                                  diagnostic calls)                          */
+    LBM_ERR_STATE = -5         /* call out of order (e.g. step before init)   */
+} lbm_status;
+
+/* Storage of the populations.  The device always stores the deviations
+ * g = f - w rho0 (w: lattice weights); collisions run in FP64 for LBM_FP64
+ * and in FP32 otherwise.  The FP16/BF16 forms store round-to-nearest-even
+ * (sigma * g) with a per-run power-of-two scale sigma. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_DEV = 2, LBM_BF16_DEV = 3 } lbm_precision;
+
+/* LBM_STREAM_AA: one array, updated in place with the AA access pattern
+ *   (even steps read and write a cell's own slots, odd steps its neighbours').
+ * LBM_STREAM_AB: two arrays, pull streaming from one into the other. */
+typedef enum { LBM_STREAM_AA = 0, LBM_STREAM_AB = 1 } lbm_streaming;
+
+/* Initial velocity field; the initial populations are the second-order
+ * equilibrium of App. A eq. feq at rho = rho0 and that velocity.
+ *   NOISE: u_a = A (2U - 1), U = (splitmix64(splitmix64(seed) ^ (3c + a)) >> 11) 2^-53
+ *   TGV3D: u = A sin X cos Y cos Z, v = -A cos X sin Y cos Z, w = 0
+ *          (X = 2 pi x/nx, ...; the Taylor-Green start of Sec. 2.2 and 3.1)
+ *   TGV2D: u = A sin X cos Y, v = -A cos X sin Y, w = 0
+ *   SHEAR: u = A sin Y
+ *   REST : u = 0 */
+typedef enum {
+    LBM_INIT_NOISE = 0, LBM_INIT_TGV3D = 1, LBM_INIT_TGV2D = 2,
+    LBM_INIT_SHEAR = 3, LBM_INIT_REST = 4
+} lbm_init_kind;
+
+/* One Fourier mode of the static body force (the general form of Sec. 2.2
+ * eq. forcing_pattern):  F(x) += amp * sin(2 pi (k0 x/nx + k1 y/ny + k2 z/nz) + phase).
+ * |k0| <= 2 is required (the force is evaluated per cell from x-harmonics 1
+ * and 2 and a per-(y,z) coefficient table); k1 and k2 are free. */
+typedef struct {
+    int32_t k[3];
+    int32_t reserved;   /* must be 0 */
+    double amp[3];
+    double phase;
+} lbm_force_mode;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* lattice size, each >= 1, nx*ny*nz < 2^31     */
+    int32_t precision;       /* lbm_precision                                 */
+    int32_t streaming;       /* lbm_streaming                                 */
+    int32_t smag_form;       /* 0: nu_t = C |S| (the paper's linear constant, */
+                             /*    eq. eddy_visc); 1: nu_t = C^2 |S|          */
+    double tau0;             /* bare relaxation time 1/s_nu, > 1/2            */
+    double smag_C;           /* Smagorinsky constant C >= 0; 0 gives DNS-MRT  */
+    double rho0;             /* reference density (1 in the paper), > 0       */
+    double s_e, s_eps, s_q, s_pi, s_m;  /* fixed rates of eq. relaxation-matrix:
+                                           1.19, 1.4, 1.2, 1.4, 1.98         */
+    double storage_scale;    /* sigma for FP16/BF16 storage; 0 selects the
+                                default (2^15 for FP16, 1 for BF16)           */
+    int32_t n_force_modes;   /* 0..64                                         */
+    int32_t steps_per_graph; /* steps captured per HIP graph in lbm_step
+                                (even, 2..1024); 0 disables graphs            */
+    const lbm_force_mode* force_modes; /* copied at create                   */
+    void* hip_stream;        /* hipStream_t to run on; NULL = null stream     */
+    void* device_buffer;     /* optional caller-owned device memory for the
+                                population state (e.g. a torch tensor), at
+                                least lbm_required_bytes() bytes, 256-B
+                                aligned; kept alive by the caller until
+                                lbm_destroy.  NULL: the library allocates.   */
+    uint64_t device_buffer_bytes;
+} lbm_config;
+
+typedef struct lbm_handle lbm_handle;
+typedef struct lbm_batch lbm_batch;
+
+/* FP64 statistics of the state after the current step (Sec. 5.1 reports
+ * domain statistics of tau_e - 1/2).  theta = tau_e - 1/2 and K_t = sqrt(3) theta
+ * per cell; var is the population variance, skew = mu3/var^1.5,
+ * flat = mu4/var^2 (NaN when var = 0). */
+typedef struct {
+    int64_t n_cells;
+    int64_t steps;            /* steps done when the statistics were taken   */
+    double theta_mean, theta_var, theta_skew, theta_flat, theta_min, theta_max;
+    double kt_mean, kt_var, kt_skew, kt_flat, kt_min, kt_max;
+    double mass;              /* sum of rho over cells                       */
+    double momentum[3];       /* sum of rho u (with the half-force shift)     */
+    double energy;            /* (1/2) <u.u>, unweighted domain mean          */
+    double energy_rho;        /* (1/2) <rho u.u>                              */
+    int64_t n_nonfinite;      /* cells whose populations or tau_e are NaN/Inf */
+} lbm_stats;
+
+/* Fill *cfg with the paper's defaults: 32^3, FP32, AA, tau0 = 0.51, C = 0.1,
+ * linear C, rho0 = 1, rates 1.19/1.4/1.2/1.4/1.98, no forcing, 64 steps per
+ * graph, null stream, library-owned memory. */
+void lbm_config_default(lbm_config* cfg);
+
+/* Bytes of device memory the population state needs (one array for AA, two
+ * for AB, each direction plane padded to 256 B); 0 if cfg is invalid. */
+size_t lbm_required_bytes(const lbm_config* cfg);
+
+/* Validate cfg, allocate the state and the small per-lattice tables on the
+ * current HIP device, evaluate the forcing tables on the device.  The state
+ * is undefined until lbm_init_seeded or lbm_set_populations.
+ * Errors: INVALID_ARG (cfg), OUT_OF_MEMORY, DEVICE.  *out is NULL on error. */
+lbm_status lbm_create(const lbm_config* cfg, lbm_handle** out);
+
+/* Set f(x, 0) = f_eq(rho0, u0(x)) (App. A eq. feq) for the velocity of
+ * `kind` (lbm_init_kind) and amplitude A; resets the step count to 0. */
+lbm_status lbm_init_seeded(lbm_handle* h, int32_t kind, double amplitude, uint64_t seed);
+
+/* Advance n >= 0 steps of eq. mrt_les_guo, asynchronously on the stream.
+ * Full graphs of steps_per_graph steps are replayed, the rest is launched. */
+lbm_status lbm_step(lbm_handle* h, int64_t n);
+
+/* rho[c] and u[a * ncells + c] (a = x, y, z) of the current state, with the
+ * half-force velocity of eq. guo_velocity.  Host arrays of ncells and
+ * 3*ncells doubles; either may be NULL.  Synchronises. */
+lbm_status lbm_moments(lbm_handle* h, double* rho, double* u);
+
+/* Domain statistics of theta and K_t plus mass, momentum and energy, reduced
+ * on the device in FP64 in a fixed order (bitwise reproducible).  tau_e is
+ * computed by the same device code as the step.  Returns LBM_ERR_UNSTABLE
+ * (with *out filled) when any cell is non-finite.  Synchronises. */
+lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out);
+
+/* Per-cell K_t = sqrt(3) (tau_e - 1/2) of the current state, host float[ncells].
+ * Synchronises. */
+lbm_status lbm_kt_field(lbm_handle* h, float* kt);
+
+/* Canonical full populations f[a * ncells + c] of the current state (host,
+ * 19 * ncells doubles).  Synchronises. */
+lbm_status lbm_get_populations(lbm_handle* h, double* f);
+
+/* Replace the state by the full populations f[a * ncells + c] (host, 19 *
+ * ncells doubles) — converted to the storage precision — keeping the step
+ * count.  Synchronises. */
+lbm_status lbm_set_populations(lbm_handle* h, const double* f);
+
+/* Canonical full populations of the listed cells: out[i * 19 + a] for cell
+ * cells[i] (0 <= cells[i] < ncells).  Host arrays.  Synchronises. */
+lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n, double* out);
+
+/* Checkpoint / resume in the storage format: lbm_state_bytes() bytes of
+ * opaque state (host memory) plus the step count.  Restoring into a handle
+ * created with the same config reproduces the run bitwise.  Both synchronise.
+ * INVALID_ARG if `bytes` differs from lbm_state_bytes(). */
+size_t lbm_state_bytes(const lbm_handle* h);
+lbm_status lbm_save_state(lbm_handle* h, void* host, size_t bytes, int64_t* steps);
+lbm_status lbm_load_state(lbm_handle* h, const void* host, size_t bytes, int64_t steps);
+
+/* Wait for all work issued on the handle's stream; DEVICE on kernel errors. */
+lbm_status lbm_synchronize(lbm_handle* h);
+
+int64_t lbm_steps_done(const lbm_handle* h);
+int64_t lbm_num_cells(const lbm_handle* h);
+
+/* Release everything the handle owns (not a caller-provided device buffer).
+ * NULL is allowed.  Synchronises the stream first. */
+void lbm_destroy(lbm_handle* h);
+
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(const lbm_handle* h);
+
+/* ---- Batched stepping of independent lattices (continuous batching) ------
+ * A batch steps up to max_slots handles with one kernel launch per step: the
+ * launch covers every slot's cells through a device-side slot table, so
+ * independent runs of different sizes and parameters share the GPU.  The
+ * handles must be FP32 with AA streaming, initialised, and created on the
+ * batch's stream; each result is bitwise the same whether its handle is
+ * stepped alone or with others.  Launches are captured once in a HIP graph of
+ * steps_per_graph launches whose kernels read the slot table from device
+ * memory, so changing the set of handles between calls does not recapture.
+ * Calls that overlap on one batch must not be made from several threads.
+ *
+ * lbm_batch_create: max_slots in 1..1024; steps_per_graph even in 2..1024,
+ *   or 0 for plain launches; hip_stream as in lbm_config.
+ * lbm_batch_step: advance hs[i] by steps[i] (0 <= steps[i] <= steps_per_graph,
+ *   or any >= 0 when steps_per_graph is 0) for i < n <= max_slots, handles
+ *   distinct.  Asynchronous; INVALID_ARG (nothing launched) on a bad argument.
+ * lbm_batch_destroy: NULL allowed; synchronises the stream first. */
+lbm_status lbm_batch_create(int32_t max_slots, int32_t steps_per_graph, void* hip_stream,
+                            lbm_batch** out);
+lbm_status lbm_batch_step(lbm_batch* b, lbm_handle* const* hs, const int32_t* steps, int32_t n);
+const char* lbm_batch_last_error(const lbm_batch* b);
+void lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H_ */

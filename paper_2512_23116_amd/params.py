@@ -1,0 +1,29 @@
+"""Lattice parameters from the physical ones (product side).
+
+Lattice units throughout: delta_x = delta_t = rho0 = 1, c_s^2 = 1/3.
+"""
+from .inputs import random_solenoidal_modes
+
+U0 = 0.043        # characteristic velocity, Sec. 3.1
+RE = 2.0e4        # Reynolds number of the DNS/LES pair, Sec. 4
+C_F = 0.2         # forcing constant, eq. forcing_amplitude
+
+
+def tau0_from_re(N, Re=RE, U0=U0):
+    """Re = U0 N / nu0 (Sec. 3.1) and nu0 = (tau0 - 1/2)/3 (eq. bare_viscosity)."""
+    return 0.5 + 3.0 * U0 * N / Re
+
+
+def forcing_amplitude(N, U0=U0, C_f=C_F, rho=1.0):
+    """F0 = C_f rho U0^2 / N (eq. forcing_amplitude)."""
+    return C_f * rho * U0 * U0 / N
+
+
+def forced_hit(N, C=0.1, force_seed=1234, init_seed=42, noise=1e-3, Re=RE):
+    """The forced-HIT LES workload: N^3 periodic, tau0 for Re = 2e4 at U0 = 0.043,
+    Smagorinsky C, solenoidal forcing on all shells |k| <= 2 with seeded phases and
+    the paper's forcing power, start from rest plus seeded velocity noise."""
+    F0 = forcing_amplitude(N)
+    return dict(N=N, tau0=tau0_from_re(N, Re), C=C, F0=F0,
+                modes=random_solenoidal_modes(F0, force_seed),
+                noise=noise, init_seed=init_seed)

@@ -1,0 +1,211 @@
+"""Continuous-batching request loop for independent LES runs on one GPU.
+
+Requests (lattice size, Smagorinsky C, tau0, forcing seed, step count) arrive
+over time.  The loop admits a waiting request as soon as a slot is free and its
+population state fits the HBM budget, keeps every admitted lattice resident on
+the device, and advances all active lattices together with ``lbm_batch_step``
+(one captured HIP graph of ``steps_per_graph`` batched launches per call).
+Requests that arrive while others run join at the next call; finished ones
+leave and free their slot and memory.  Latency = completion - arrival.
+
+The engine behind the loop is pluggable: ``GpuEngine`` drives liblbm.so,
+``FakeEngine`` simulates durations on the host so the scheduling logic is
+tested without a GPU.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import params
+from .inputs import random_solenoidal_modes
+
+
+@dataclass
+class Request:
+    rid: int
+    N: int
+    C: float
+    tau0: float
+    force_seed: int
+    init_seed: int
+    arrival: float
+    steps: int = 5000
+    # filled by the loop
+    admit: float = None
+    complete: float = None
+    done_steps: int = 0
+    error: str = None
+    result: dict = field(default_factory=dict)
+
+    @property
+    def cells(self):
+        return self.N ** 3
+
+    @property
+    def state_bytes(self):
+        return 19 * self.cells * 4          # FP32, AA in place
+
+    @property
+    def latency(self):
+        return None if self.complete is None else self.complete - self.arrival
+
+
+class GpuEngine:
+    """Runs requests as FP32/AA lattices batched through liblbm.so."""
+
+    def __init__(self, max_slots=16, steps_per_graph=64, noise=1e-3):
+        import torch
+        from . import lbm
+        self.lbm = lbm
+        self.stream = torch.cuda.Stream()
+        self.G = steps_per_graph
+        self.noise = noise
+        self.batch = lbm.lbm_batch_create(max_slots, steps_per_graph, self.stream.cuda_stream)
+        self.lat = {}
+
+    def admit(self, r):
+        F0 = params.forcing_amplitude(r.N)
+        modes = random_solenoidal_modes(F0, r.force_seed)
+        lat = self.lbm.Lattice((r.N, r.N, r.N), r.tau0, r.C, modes, precision="fp32",
+                               streaming="aa", steps_per_graph=self.G, stream=self.stream)
+        lat.init(self.lbm.LBM_INIT_NOISE, self.noise, r.init_seed)
+        self.lat[r.rid] = lat
+
+    def step(self, reqs, steps):
+        self.lbm.lbm_batch_step(self.batch, [self.lat[r.rid].handle for r in reqs], steps)
+
+    def wait(self):
+        self.stream.synchronize()
+
+    def finish(self, r, keep_state=False):
+        lat = self.lat.pop(r.rid)
+        st = lat.stats(allow_unstable=True)
+        r.result = dict(stats=st)
+        if keep_state:
+            r.result["state"] = lat.save()[0]
+        lat.close()
+
+    def close(self):
+        self.wait()
+        for lat in self.lat.values():
+            lat.close()
+        self.lat.clear()
+        self.lbm.lbm_batch_destroy(self.batch)
+
+
+class FakeEngine:
+    """Host-only engine: a call takes sum(cells * steps) / rate seconds."""
+
+    def __init__(self, rate=3e10, max_slots=16, steps_per_graph=64, fail_rids=()):
+        self.rate = rate
+        self.G = steps_per_graph
+        self.fail_rids = set(fail_rids)
+        self.active = {}
+        self.calls = []
+
+    def admit(self, r):
+        if r.rid in self.fail_rids:
+            raise RuntimeError(f"admission of request {r.rid} failed")
+        self.active[r.rid] = r
+
+    def step(self, reqs, steps):
+        self.calls.append([(r.rid, s) for r, s in zip(reqs, steps)])
+        time.sleep(sum(r.cells * s for r, s in zip(reqs, steps)) / self.rate)
+
+    def wait(self):
+        pass
+
+    def finish(self, r, keep_state=False):
+        self.active.pop(r.rid, None)
+        r.result = dict(stats=None)
+
+    def close(self):
+        self.active.clear()
+
+
+def serve(requests, engine, max_slots=16, hbm_budget=80e9, keep_state=False, clock=None):
+    """Run the request loop until every request has completed or failed.
+
+    Returns a summary dict: p50/p99 latency, aggregate MLUPS over the busy
+    span, GPU-busy fraction of the loop, and the per-request records.
+    """
+    clock = clock or time.perf_counter
+    pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    waiting = []          # FIFO of arrived, not admitted requests
+    active = []
+    used = 0
+    t0 = clock()
+    busy = 0.0
+    i = 0
+    cell_updates = 0
+    G = engine.G
+    while i < len(pending) or waiting or active:
+        now = clock() - t0
+        while i < len(pending) and pending[i].arrival <= now:
+            waiting.append(pending[i])
+            i += 1
+        # admission: FIFO, by free slot and HBM budget
+        while waiting and len(active) < max_slots and used + waiting[0].state_bytes <= hbm_budget:
+            r = waiting.pop(0)
+            try:
+                engine.admit(r)
+            except Exception as e:          # a request that cannot start fails alone
+                r.error = str(e)
+                r.complete = clock() - t0
+                continue
+            r.admit = clock() - t0
+            used += r.state_bytes
+            active.append(r)
+        if waiting and not active and waiting[0].state_bytes > hbm_budget:
+            r = waiting.pop(0)
+            r.error = "state larger than the HBM budget"
+            r.complete = clock() - t0
+            continue
+        if not active:
+            if i < len(pending):
+                delay = pending[i].arrival - (clock() - t0)
+                if delay > 0:
+                    time.sleep(min(delay, 0.01))
+            continue
+        steps = [min(G, r.steps - r.done_steps) for r in active]
+        tb = clock()
+        engine.step(active, steps)
+        engine.wait()
+        busy += clock() - tb
+        for r, s in zip(active, steps):
+            r.done_steps += s
+            cell_updates += r.cells * s
+        still = []
+        for r in active:
+            if r.done_steps >= r.steps:
+                engine.finish(r, keep_state)
+                r.complete = clock() - t0
+                used -= r.state_bytes
+            else:
+                still.append(r)
+        active = still
+    t_end = clock() - t0
+    lat = np.array([r.latency for r in requests if r.error is None and r.latency is not None])
+    first = min(r.arrival for r in requests) if requests else 0.0
+    span = max(t_end - first, 1e-12)
+    return dict(
+        n=len(requests), failed=sum(r.error is not None for r in requests),
+        p50_s=float(np.percentile(lat, 50)) if lat.size else None,
+        p99_s=float(np.percentile(lat, 99)) if lat.size else None,
+        mean_s=float(lat.mean()) if lat.size else None,
+        wall_s=t_end, busy_s=busy, busy_frac=busy / span,
+        cell_updates=cell_updates,
+        aggregate_mlups=cell_updates / span / 1e6,
+        busy_mlups=cell_updates / max(busy, 1e-12) / 1e6,
+    )
+
+
+def make_requests(n=64, seed=2024, steps=5000, rate=None, sizes=(32, 48, 64, 96, 128)):
+    """The seeded serving workload: sizes uniform over ``sizes``, C in [0.08, 0.18],
+    tau0 in [0.505, 0.55], per-request forcing and noise seeds, Poisson arrivals."""
+    from .inputs import serving_requests
+    return [Request(rid=d["rid"], N=d["N"], C=d["C"], tau0=d["tau0"],
+                    force_seed=d["force_seed"], init_seed=d["init_seed"],
+                    arrival=d["arrival"], steps=steps)
+            for d in serving_requests(n, seed, sizes=sizes, rate=rate)]

@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI library (no GPU work is launched)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2512_23116_amd import lbm as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("liblbm.so is not built (run __graft_entry__.build())")
+    m.lib()
+    return m
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+
+
+def test_header_declares_what_the_library_exports(lbm):
+    declared = header_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T lbm_" in ln}
+    assert declared == exported
+    assert declared == set(lbm.EXPORTS)
+    for name in declared:
+        assert hasattr(lbm.lib(), name)
+
+
+def test_header_compiles_as_c_and_struct_layout_matches(lbm, tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "lbm.h"\n#include <stddef.h>\n#include <stdio.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(lbm_config),'
+                   ' sizeof(lbm_force_mode), sizeof(lbm_stats),'
+                   ' offsetof(lbm_config, device_buffer_bytes));return 0;}\n')
+    exe = tmp_path / "t"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                    str(src), "-o", str(exe)], check=True)
+    sizes = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                            check=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(lbm.lbm_config), ctypes.sizeof(lbm.lbm_force_mode),
+                     ctypes.sizeof(lbm.lbm_stats), lbm.lbm_config.device_buffer_bytes.offset]
+
+
+def test_config_defaults_and_required_bytes(lbm):
+    c = lbm.lbm_config_default()
+    assert (c.nx, c.ny, c.nz) == (32, 32, 32)
+    assert c.tau0 == 0.51 and c.smag_C == 0.1 and c.rho0 == 1.0
+    assert (c.s_e, c.s_eps, c.s_q, c.s_pi, c.s_m) == (1.19, 1.4, 1.2, 1.4, 1.98)
+    assert c.precision == lbm.LBM_FP32 and c.streaming == lbm.LBM_STREAM_AA
+    plane = 32 ** 3
+    assert lbm.lbm_required_bytes(c) == 19 * plane * 4
+    c.streaming = lbm.LBM_STREAM_AB
+    c.precision = lbm.LBM_FP64
+    assert lbm.lbm_required_bytes(c) == 2 * 19 * plane * 8
+    c.nx, c.ny, c.nz = 100, 100, 100
+    c.precision, c.streaming = lbm.LBM_FP32, lbm.LBM_STREAM_AA
+    assert lbm.lbm_required_bytes(c) == 19 * 1000064 * 4       # planes padded to 128 cells
+    c.nx = c.ny = c.nz = 800
+    assert lbm.lbm_required_bytes(c) == 19 * 512000000 * 4     # 38.9 GB in place
+    c.precision = lbm.LBM_BF16_DEV
+    assert lbm.lbm_required_bytes(c) == 19 * 512000000 * 2
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("tau0", 0.5), ("tau0", float("nan")), ("smag_C", -0.1), ("precision", 7),
+    ("streaming", 2), ("smag_form", 2), ("rho0", 0.0), ("s_m", 2.0), ("storage_scale", 3.0),
+    ("steps_per_graph", 3), ("steps_per_graph", 2048), ("n_force_modes", 65),
+])
+def test_invalid_configs_are_rejected_on_the_host(lbm, field, value):
+    c = lbm.lbm_config_default()
+    setattr(c, field, value)
+    assert lbm.lbm_required_bytes(c) == 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(c)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+
+
+def test_too_many_cells_and_bad_modes_are_rejected(lbm):
+    c = lbm.lbm_config_default()
+    c.nx = c.ny = c.nz = 1291          # 1291^3 >= 2^31
+    assert lbm.lbm_required_bytes(c) == 0
+    c = lbm.lbm_config_default()
+    modes = lbm.make_modes([((3, 0, 0), (1e-5, 0, 0), 0.0)])
+    c.n_force_modes = 1
+    c.force_modes = ctypes.cast(modes, ctypes.POINTER(lbm.lbm_force_mode))
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(c)
+    assert "k[0]" in str(e.value)
+
+
+def test_status_strings(lbm):
+    L = lbm.lib()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.lbm_status_string(s)
+    assert L.lbm_last_error(None) is not None
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    from paper_2512_23116_amd import lbm as m
+    monkeypatch.setattr(m, "_lib", None)
+    monkeypatch.setattr(m, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        m.lib()

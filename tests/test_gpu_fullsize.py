@@ -1,0 +1,79 @@
+"""Full-size checks in the configuration the benchmark times (FP32, AA,
+64-step graphs): sampled cells against the oracle's per-cell collision, and
+conservation over the whole lattice."""
+import numpy as np
+import pytest
+
+from oracle import d3q19 as OL
+from paper_2512_23116_amd import params
+from tests.helpers import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2512_23116_amd import lbm as m
+    m.lib()
+    return m
+
+
+def _sample_cells(shape, n, seed):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx - 1, 0, nz // 2), (0, ny - 1, 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, (nx, ny, nz))) for _ in range(n)]
+    return pts
+
+
+def _cell(x, y, z, shape):
+    nz, ny, nx = shape
+    return (x % nx) + nx * ((y % ny) + ny * (z % nz))
+
+
+def sampled_step_check(lat, olat, shape, pts):
+    """f_i(x, n+1) from the GPU against the oracle's collision of the cell
+    x - c_i at step n, for every sampled x and every i."""
+    nbr = []
+    for (x, y, z) in pts:
+        for a in range(19):
+            cx, cy, cz = OL.C[a]
+            nbr.append(_cell(x - cx, y - cy, z - cz, shape))
+    before = lat.sample(np.array(nbr))
+    lat.step(1)
+    after = lat.sample(np.array([_cell(x, y, z, shape) for (x, y, z) in pts]))
+    worst = 0.0
+    scale = np.abs(after - OL.W).max()
+    for j, (x, y, z) in enumerate(pts):
+        for a in range(19):
+            cx, cy, cz = OL.C[a]
+            xs, ys, zs = x - cx, y - cy, z - cz
+            F = olat.force_at(xs % shape[2], ys % shape[1], zs % shape[0])
+            fstar, _, _, _ = olat.collide_cell(before[j * 19 + a], F)
+            worst = max(worst, abs(fstar[a] - after[j, a]))
+    return worst / scale
+
+
+@pytest.mark.parametrize("N", [100, 800])
+def test_forced_hit_fullsize(lbm, orc, N):
+    shape = (N, N, N)
+    cfg = params.forced_hit(N)
+    lat = lbm.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], precision="fp32",
+                      steps_per_graph=64)
+    lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
+    st0 = lat.stats()
+    lat.step(129)          # two graph replays and a plain launch (odd parity next)
+    st1 = lat.stats()
+    olat = orc.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"])
+    err = sampled_step_check(lat, olat, shape, _sample_cells(shape, 40, N))
+    print(f"{N}^3: sampled one-step error {err:.3e}; mass drift "
+          f"{abs(st1['mass'] - st0['mass']) / st0['mass']:.2e}", flush=True)
+    assert err <= 1e-5
+    # mass is conserved up to FP32 rounding of the stored deviations
+    assert abs(st1["mass"] - st0["mass"]) <= 1e-9 * st0["mass"]
+    assert st1["n_nonfinite"] == 0 and st1["theta_min"] >= cfg["tau0"] - 0.5 - 1e-9
+    lat.step(1)
+    err = sampled_step_check(lat, olat, shape, _sample_cells(shape, 40, N + 1))
+    assert err <= 1e-5
+    lat.close()
