@@ -146,6 +146,25 @@ def run_serving(n_req, steps, seed=2024):
                 capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80)
 
 
+def profile_run(lbm, params, args):
+    """Known-size copy (the counter calibration), then a few plain step launches."""
+    import torch
+    n = 1 << 28                      # 2^28 floats = 1 GiB read + 1 GiB written per copy
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
+    log("profile: 3 copies of 1 GiB done")
+    for N, steps in ((args.N, 8), (args.large_N, 4)):
+        if N == args.large_N and args.no_large:
+            continue
+        run_lattice(lbm, params, N, args.precision, args.streaming, steps, 2, 0, spg=0)
+        log(f"profile: {N}^3 {args.precision} {args.streaming}, {steps} plain launches done")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +182,9 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for hardware counters: a 1 GiB copy of known size, then "
+                         "plain (graph-free) step launches at N and large-N; no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -176,6 +198,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     lbm.lib()
+    if args.profile:
+        profile_run(lbm, params, args)
+        return
 
     log(f"main: {args.N}^3 {args.precision} {args.streaming}, {args.steps} steps")
     main_run = run_lattice(lbm, params, args.N, args.precision, args.streaming, args.steps,

@@ -139,8 +139,10 @@ typedef struct {
  * graph, null stream, library-owned memory. */
 void lbm_config_default(lbm_config* cfg);
 
-/* Bytes of device memory the population state needs (one array for AA, two
- * for AB, each direction plane padded to 256 B); 0 if cfg is invalid. */
+/* Bytes of device memory the population state needs: 19 direction planes per
+ * array (one array for AA, two for AB), each plane holding nx*ny*nz cells
+ * rounded up to 64 plus 1728 cells of padding that staggers the plane starts
+ * across HBM channels; 0 if cfg is invalid. */
 size_t lbm_required_bytes(const lbm_config* cfg);
 
 /* Validate cfg, allocate the state and the small per-lattice tables on the

@@ -218,19 +218,37 @@ static inline int wrap(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-/* One collide-and-stream step from f into g (push: g[a](x + c_a) = f*[a](x)). */
-static void step_once(const orc_params* p, const double* f, double* g) {
+/* The body force is static (Sec. 2.2), so it is evaluated once per call into
+ * F[3][cells] and reused by every step of the call. */
+static void force_field(const orc_params* p, double* F) {
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const size_t nc = (size_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z) {
-        double fc[Q], fs[Q], F[3];
+        double Fc[3];
+        for (int y = 0; y < ny; ++y) {
+            for (int x = 0; x < nx; ++x) {
+                const size_t c = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+                orc_force_at(p, x, y, z, Fc);
+                F[c] = Fc[0]; F[nc + c] = Fc[1]; F[2 * nc + c] = Fc[2];
+            }
+        }
+    }
+}
+
+/* One collide-and-stream step from f into g (push: g[a](x + c_a) = f*[a](x)). */
+static void step_once(const orc_params* p, const double* F, const double* f, double* g) {
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const size_t nc = (size_t)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z) {
+        double fc[Q], fs[Q], Fc[3];
         for (int y = 0; y < ny; ++y) {
             for (int x = 0; x < nx; ++x) {
                 const size_t c = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
                 for (int a = 0; a < Q; ++a) fc[a] = f[a * nc + c];
-                orc_force_at(p, x, y, z, F);
-                orc_collide_cell(p, fc, F, fs, NULL, NULL, NULL);
+                Fc[0] = F[c]; Fc[1] = F[nc + c]; Fc[2] = F[2 * nc + c];
+                orc_collide_cell(p, fc, Fc, fs, NULL, NULL, NULL);
                 for (int a = 0; a < Q; ++a) {
                     const int xd = wrap(x + CV[a][0], nx);
                     const int yd = wrap(y + CV[a][1], ny);
@@ -245,14 +263,19 @@ static void step_once(const orc_params* p, const double* f, double* g) {
 /* Advance f by nsteps; work has the same size as f (19 * nx*ny*nz doubles). */
 int orc_step(const orc_params* p, double* f, double* work, int64_t nsteps) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || nsteps < 0) return -1;
-    const size_t n = (size_t)Q * p->nx * p->ny * p->nz;
+    const size_t nc = (size_t)p->nx * p->ny * p->nz;
+    const size_t n = (size_t)Q * nc;
+    double* F = (double*)malloc(3 * nc * sizeof(double));
+    if (!F) return -2;
+    force_field(p, F);
     double* a = f;
     double* b = work;
     for (int64_t s = 0; s < nsteps; ++s) {
-        step_once(p, a, b);
+        step_once(p, F, a, b);
         double* t = a; a = b; b = t;
     }
     if (a != f) memcpy(f, a, n * sizeof(double));
+    free(F);
     return 0;
 }
 

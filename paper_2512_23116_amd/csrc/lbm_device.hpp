@@ -117,9 +117,19 @@ __device__ __forceinline__ uint32_t block_id(const LatticeArgs& L) {
     return b;
 }
 
+// Address of element c of plane `slot`: the 64-bit plane base is uniform
+// (SGPRs) and the per-lane part is a 32-bit byte offset (plane bytes < 2^32 is
+// enforced at create), which maps to global loads with a scalar base.
+template <typename T>
+__device__ __forceinline__ T* elem_ptr(T* base, int slot, uint64_t plane, uint32_t c) {
+    using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+    B* pb = (B*)(base + (uint64_t)slot * plane);
+    return (T*)(pb + (uint32_t)(c * (uint32_t)sizeof(T)));
+}
+
 // Location of the pre-collision f_i(x) for pattern PAT: slot and cell.
 //   AA_EVEN: (i, x)   AA_ODD: (opp i, x - c_i)   AB: (i, x - c_i)
-template <class Cd, int PAT>
+template <class Cd, int PAT, bool kNT = false>
 __device__ __forceinline__ void load_cell(const typename Cd::T* base, uint64_t plane, uint32_t cell,
                                           const Nbr& nb, typename Cd::R (&g)[19],
                                           typename Cd::R inv_s) {
@@ -127,13 +137,15 @@ __device__ __forceinline__ void load_cell(const typename Cd::T* base, uint64_t p
         constexpr int i = decltype(I)::value;
         constexpr int slot = (PAT == PAT_AA_ODD) ? opp_of(i) : i;
         const uint32_t c = (PAT == PAT_AA_EVEN) ? cell : cell + (uint32_t)off_minus<i>(nb);
-        g[i] = dec<Cd>(base[(uint64_t)slot * plane + c], inv_s);
+        const typename Cd::T* p = elem_ptr(base, slot, plane, c);
+        if constexpr (kNT) g[i] = dec<Cd>(__builtin_nontemporal_load(p), inv_s);
+        else g[i] = dec<Cd>(*p, inv_s);
     });
 }
 
 // Where the post-collision f*_i(x) goes for pattern PAT (the pattern the step
 // reads with): AA_EVEN -> (opp i, x); AA_ODD -> (i, x + c_i); AB -> (i, x) of dst.
-template <class Cd, int PAT>
+template <class Cd, int PAT, bool kNT = false>
 __device__ __forceinline__ void store_cell(typename Cd::T* base, uint64_t plane, uint32_t cell,
                                            const Nbr& nb, const typename Cd::R (&g)[19],
                                            typename Cd::R s) {
@@ -141,17 +153,26 @@ __device__ __forceinline__ void store_cell(typename Cd::T* base, uint64_t plane,
         constexpr int i = decltype(I)::value;
         constexpr int slot = (PAT == PAT_AA_EVEN) ? opp_of(i) : i;
         const uint32_t c = (PAT == PAT_AA_ODD) ? cell + (uint32_t)off_minus<opp_of(i)>(nb) : cell;
-        base[(uint64_t)slot * plane + c] = enc<Cd>(g[i], s);
+        typename Cd::T* p = elem_ptr(base, slot, plane, c);
+        if constexpr (kNT) __builtin_nontemporal_store(enc<Cd>(g[i], s), p);
+        else *p = enc<Cd>(g[i], s);
     });
 }
 
 template <typename R>
-__device__ __forceinline__ CollideConst<R> collide_const(const LatticeArgs& L) {
-    CollideConst<R> k;
-    k.tau0 = (R)L.tau0; k.c3 = (R)L.c3; k.a_e = (R)L.a_e; k.b9 = (R)L.b9;
-    k.s_e = (R)L.s_e; k.s_eps = (R)L.s_eps; k.s_q = (R)L.s_q; k.s_pi = (R)L.s_pi;
-    k.s_m = (R)L.s_m; k.rho0 = (R)L.rho0;
-    return k;
+__device__ __forceinline__ const CollideConst<R>& collide_const(const LatticeArgs& L) {
+    if constexpr (std::is_same_v<R, double>) return L.kd;
+    else return L.kf;
+}
+template <typename R>
+__device__ __forceinline__ R scale_of(const LatticeArgs& L) {
+    if constexpr (std::is_same_v<R, double>) return L.sigma;
+    else return L.sigma_f;
+}
+template <typename R>
+__device__ __forceinline__ R inv_scale_of(const LatticeArgs& L) {
+    if constexpr (std::is_same_v<R, double>) return L.inv_sigma;
+    else return L.inv_sigma_f;
 }
 
 // Body force at (x, row) from the row coefficients and the x-harmonic table:
@@ -173,18 +194,26 @@ __device__ __forceinline__ void force_at(const LatticeArgs& L, const CellPos& p,
 
 // One cell of the fused stream-and-collide step (eq. mrt_les_guo): gather the
 // 19 pre-collision populations of pattern PAT, collide, scatter.
-template <class Cd, int PAT>
+// NT: bit 0 = non-temporal loads, bit 1 = non-temporal stores.
+template <class Cd, int PAT, int NT = 0>
 __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
     using T = typename Cd::T;
     using R = typename Cd::R;
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, (R)L.inv_sigma);
+    load_cell<Cd, PAT, (NT & 1) != 0>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     collide<R, true>(g, Fx, Fy, Fz, collide_const<R>(L));
-    store_cell<Cd, PAT>((T*)(PAT == PAT_AB ? L.b : L.a), L.plane, cell, nb, g, (R)L.sigma);
+    // Rebuild the store addresses from here: an empty register barrier on the
+    // cell index keeps the compiler from holding 19 precomputed 64-bit store
+    // addresses live across the collision (38 VGPRs), so stores use the same
+    // scalar-base + 32-bit-offset form as the loads.
+    uint32_t cs = cell;
+    asm volatile("" : "+v"(cs));
+    store_cell<Cd, PAT, (NT & 2) != 0>((T*)(PAT == PAT_AB ? L.b : L.a), L.plane, cs, nb, g,
+                                       scale_of<R>(L));
 }
 
 }  // namespace lbm

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "d3q19_mrt.hpp"
 
 namespace lbm {
 
@@ -29,15 +30,18 @@ DivMagic make_div_magic(uint32_t d);
 struct LatticeArgs {
     void* a;                 // population array (AA: the only one; AB: current source)
     void* b;                 // AB: destination; AA: == a
-    uint64_t plane;          // elements per direction plane (padded)
+    uint64_t plane;          // elements per direction plane (padded); plane bytes < 2^32
     uint32_t nx, ny, nz, nxy, ncell;
-    DivMagic mx, my;        // division by nx (cell -> row) and ny (row -> z)
+    DivMagic mx, my;         // division by nx (cell -> row) and ny (row -> z)
     const void* rowc;        // force row coefficients [ny*nz][16] in R, or null
     const void* xtab;        // [nx][4] sin/cos of the first two x harmonics, in R
-    // collision constants, double; converted to R in the kernel prologue
-    double tau0, c3, a_e, b9, s_e, s_eps, s_q, s_pi, s_m, rho0;
+    CollideConst<double> kd; // collision constants for FP64 arithmetic
+    CollideConst<float> kf;  // the same rounded to FP32 on the host
+    double tau0, rho0;
     double sigma, inv_sigma; // FP16/BF16 storage scale
+    float sigma_f, inv_sigma_f;
     int32_t xcd_remap;       // remap block ids so each XCD walks a contiguous range
+    int32_t nt_mode;         // step kernel: bit 1 non-temporal stores
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.

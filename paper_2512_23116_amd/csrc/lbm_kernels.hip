@@ -19,11 +19,11 @@
 namespace lbm {
 
 // ------------------------------------------------------------ the step ---
-template <class Cd, int PAT>
+template <class Cd, int PAT, int NT>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs L) {
     const uint32_t cell = block_id(L) * 256u + threadIdx.x;
     if (cell >= L.ncell) return;
-    step_cell<Cd, PAT>(L, cell);
+    step_cell<Cd, PAT, NT>(L, cell);
 }
 
 // ----------------------------------------------------- diagnostics ---
@@ -53,13 +53,13 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
     for (int j = 0; j < 13; ++j) acc[j] = 0.0;
     acc[4] = INFINITY;
     acc[5] = -INFINITY;
-    const CollideConst<R> k = collide_const<R>(L);
+    const CollideConst<R>& k = collide_const<R>(L);
     for (uint32_t cell = blockIdx.x * 256u + threadIdx.x; cell < L.ncell;
          cell += gridDim.x * 256u) {
         const CellPos p = decode(cell, L);
         const Nbr nb = make_nbr(p, L);
         R g[19];
-        load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, (R)L.inv_sigma);
+        load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
         bool finite = true;
 #pragma unroll
         for (int i = 0; i < 19; ++i) finite = finite && isfinite(g[i]);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_moments(LatticeArgs L, double* rho, dou
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, (R)L.inv_sigma);
+    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     const CellMacro<R> m = collide<R, false>(g, Fx, Fy, Fz, collide_const<R>(L));
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, (R)L.inv_sigma);
+    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     const CellMacro<R> m = collide<R, false>(g, Fx, Fy, Fz, collide_const<R>(L));
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_gather_plane(LatticeArgs L, int pat, in
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     const T v = ((const T*)L.a)[canon_index(pat, i, cell, nb, L.plane)];
-    out[cell] = (double)dec<Cd>(v, (R)L.inv_sigma) + w_of(i) * L.rho0;
+    out[cell] = (double)dec<Cd>(v, inv_scale_of<R>(L)) + w_of(i) * L.rho0;
 }
 
 template <class Cd>
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_scatter_plane(LatticeArgs L, int pat, i
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     const R g = (R)(in[cell] - w_of(i) * L.rho0);
-    ((T*)L.a)[canon_index(pat, i, cell, nb, L.plane)] = enc<Cd>(g, (R)L.sigma);
+    ((T*)L.a)[canon_index(pat, i, cell, nb, L.plane)] = enc<Cd>(g, scale_of<R>(L));
 }
 
 template <class Cd>
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_sample(LatticeArgs L, int pat, const in
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     const T v = ((const T*)L.a)[canon_index(pat, i, cell, nb, L.plane)];
-    out[t] = (double)dec<Cd>(v, (R)L.inv_sigma) + w_of(i) * L.rho0;
+    out[t] = (double)dec<Cd>(v, inv_scale_of<R>(L)) + w_of(i) * L.rho0;
 }
 
 // --------------------------------------------------------------- set-up ---
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_init(LatticeArgs L, int pat, int kind, 
     for (int i = 0; i < 19; ++i) {
         const double cu = cx_of(i) * u[0] + cy_of(i) * u[1] + cz_of(i) * u[2];
         const double g = w_of(i) * L.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        ((T*)L.a)[canon_index(pat, i, cell, nb, L.plane)] = enc<Cd>((R)g, (R)L.sigma);
+        ((T*)L.a)[canon_index(pat, i, cell, nb, L.plane)] = enc<Cd>((R)g, scale_of<R>(L));
     }
 }
 
@@ -359,7 +359,10 @@ hipError_t launch_step(int precision, int pat, const LatticeArgs& L, hipStream_t
     return dispatch(precision, pat, [&](auto cd, auto pt) {
         using Cd = decltype(cd);
         constexpr int P = decltype(pt)::value;
-        hipLaunchKernelGGL((k_step<Cd, P>), grid_for(L.ncell), dim3(256), 0, s, L);
+        if (L.nt_mode & 2)
+            hipLaunchKernelGGL((k_step<Cd, P, 2>), grid_for(L.ncell), dim3(256), 0, s, L);
+        else
+            hipLaunchKernelGGL((k_step<Cd, P, 0>), grid_for(L.ncell), dim3(256), 0, s, L);
         return hipGetLastError();
     });
 }

@@ -1,0 +1,132 @@
+"""Summarise rocprofv3 output for the step kernels.
+
+    python -m paper_2512_23116_amd.rocprof_summary --trace DIR [--fetch DIR --write DIR]
+        [--cmd "the profiled command"] [--traffic-out profiles/hbm_traffic.txt]
+
+``--trace`` is a ``rocprofv3 --kernel-trace --stats --output-format csv`` output
+directory: per-kernel launch counts and durations are listed per grid size
+(lattice), so even and odd AA steps and the 100^3 / 800^3 lattices are apart.
+
+``--fetch`` / ``--write`` are ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc
+WRITE_SIZE`` runs of ``bench.py --profile``.  That command first copies 1 GiB
+with a known-size copy kernel; the counters' reading for it calibrates the
+counters to bytes (FETCH_SIZE reads half of the true bytes on MI355X), and the
+calibrated bytes per step launch are compared with the algorithmic 2*19*b*N^3.
+With ``--traffic-out`` one line per lattice is appended for bench.py:
+``<N>_<precision>_<streaming> <kernel-source sha> <fetch bytes> <write bytes>``.
+"""
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, f"*{suffix}"))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def short(name):
+    return name.replace("(lbm::LatticeArgs)", "").replace("void ", "").replace("lbm::", "")
+
+
+def trace_table(d):
+    rows = _csv(d, "_kernel_trace.csv")
+    by = collections.defaultdict(list)
+    for r in rows:
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        by[(short(r["Kernel_Name"]), g)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = []
+    for (k, g), v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        out.append((k, g, len(v), statistics.mean(v) / 1e3, statistics.median(v) / 1e3,
+                    min(v) / 1e3, max(v) / 1e3))
+    return out
+
+
+def counters(d, name):
+    rows = _csv(d, "_counter_collection.csv")
+    by = collections.defaultdict(list)
+    for r in rows:
+        if r["Counter_Name"] != name:
+            continue
+        by[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return by
+
+
+def calibration(by):
+    """KiB the counter reports for the 1 GiB copy launches (largest copy grid)."""
+    copies = [(g, v) for (k, g), v in by.items() if "copyBuffer" in k or "copy" in k.lower()]
+    g, v = max(copies, key=lambda gv: gv[0])
+    return statistics.mean(v)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--cmd", default="")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--streaming", default="aa")
+    ap.add_argument("--traffic-out")
+    a = ap.parse_args()
+    b = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[a.precision]
+    if a.cmd:
+        print(f"command: {a.cmd}")
+    print(f"kernel sources sha256[:16]: {kernel_source_sha()}")
+    if a.trace:
+        print("\nkernel trace (durations in us; grid = threads launched)")
+        print(f"{'kernel':58s} {'grid':>11s} {'calls':>6s} {'mean':>10s} {'median':>10s} "
+              f"{'min':>10s} {'max':>10s}")
+        for k, g, n, mean, med, lo, hi in trace_table(a.trace):
+            print(f"{k[:58]:58s} {g:11d} {n:6d} {mean:10.2f} {med:10.2f} {lo:10.2f} {hi:10.2f}")
+    if a.fetch and a.write:
+        fb = counters(a.fetch, "FETCH_SIZE")
+        wb = counters(a.write, "WRITE_SIZE")
+        fcal = COPY_BYTES / 1024 / calibration(fb)
+        wcal = COPY_BYTES / 1024 / calibration(wb)
+        print(f"\ncounter calibration on a 1 GiB copy: FETCH_SIZE x {fcal:.4f}, "
+              f"WRITE_SIZE x {wcal:.4f}")
+        print(f"{'kernel':58s} {'cells':>11s} {'fetch GB':>9s} {'write GB':>9s} "
+              f"{'alg GB':>8s} {'ratio':>6s}")
+        per_lattice = collections.defaultdict(lambda: [0.0, 0.0, 0])
+        for (k, g), v in sorted(fb.items()):
+            if "k_step" not in k:
+                continue
+            f = statistics.mean(v) * 1024 * fcal
+            w = statistics.mean(wb[(k, g)]) * 1024 * wcal
+            cells = round(g ** (1 / 3)) ** 3     # the grid is rounded up to whole blocks
+            alg = 2 * 19 * b * cells
+            print(f"{short(k)[:58]:58s} {cells:11d} {f / 1e9:9.4f} {w / 1e9:9.4f} {alg / 1e9:8.4f} "
+                  f"{(f + w) / alg:6.3f}")
+            acc = per_lattice[g]
+            acc[0] += f
+            acc[1] += w
+            acc[2] += 1
+        if a.traffic_out:
+            sha = kernel_source_sha()
+            with open(a.traffic_out, "a") as fh:
+                for g, (f, w, n) in sorted(per_lattice.items()):
+                    N = round(g ** (1 / 3))
+                    fh.write(f"{N}_{a.precision}_{a.streaming} {sha} {f / n:.6e} {w / n:.6e} "
+                             f"k_step mean over {n} kernels\n")
+
+
+if __name__ == "__main__":
+    main()

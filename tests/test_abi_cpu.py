@@ -57,18 +57,21 @@ def test_config_defaults_and_required_bytes(lbm):
     assert c.tau0 == 0.51 and c.smag_C == 0.1 and c.rho0 == 1.0
     assert (c.s_e, c.s_eps, c.s_q, c.s_pi, c.s_m) == (1.19, 1.4, 1.2, 1.4, 1.98)
     assert c.precision == lbm.LBM_FP32 and c.streaming == lbm.LBM_STREAM_AA
-    plane = 32 ** 3
+    pad = 1728
+    plane = 32 ** 3 + pad
     assert lbm.lbm_required_bytes(c) == 19 * plane * 4
     c.streaming = lbm.LBM_STREAM_AB
     c.precision = lbm.LBM_FP64
     assert lbm.lbm_required_bytes(c) == 2 * 19 * plane * 8
     c.nx, c.ny, c.nz = 100, 100, 100
     c.precision, c.streaming = lbm.LBM_FP32, lbm.LBM_STREAM_AA
-    assert lbm.lbm_required_bytes(c) == 19 * 1000064 * 4       # planes padded to 128 cells
+    assert lbm.lbm_required_bytes(c) == 19 * (1000000 + pad) * 4
     c.nx = c.ny = c.nz = 800
-    assert lbm.lbm_required_bytes(c) == 19 * 512000000 * 4     # 38.9 GB in place
+    assert lbm.lbm_required_bytes(c) == 19 * (512000000 + pad) * 4     # 38.9 GB in place
     c.precision = lbm.LBM_BF16_DEV
-    assert lbm.lbm_required_bytes(c) == 19 * 512000000 * 2
+    assert lbm.lbm_required_bytes(c) == 19 * (512000000 + pad) * 2
+    c.nx = 7
+    assert lbm.lbm_required_bytes(c) == 19 * ((7 * 800 * 800 + 63) // 64 * 64 + pad) * 2
 
 
 @pytest.mark.parametrize("field,value", [
