@@ -3,7 +3,7 @@
 
 Prints ONE JSON line.  The headline workload is forced-HIT LES on a 100^3
 periodic lattice in FP32 with in-place AA streaming (Re = 2e4 at U0 = 0.043,
-C = 0.1, solenoidal forcing on |k| <= 2 with seeded phases, 1e-3 noise start,
+C_s = 0.1 in nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with seeded phases, 1e-3 noise start,
 on-device K_t statistics every 500 steps).  A "step" is one lattice time step:
 the fused stream-and-collide kernel over every cell.  ``value`` is MLUPS
 (million lattice-cell updates per second) over the timed steps, with the
@@ -63,7 +63,8 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
     stream = torch.cuda.Stream()
     cfg = params.forced_hit(N)
     lat = lbm.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"], precision=precision,
-                      streaming=streaming, steps_per_graph=spg, stream=stream)
+                      streaming=streaming, smag_form=cfg["smag_form"], steps_per_graph=spg,
+                      stream=stream)
     lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
     lat.step(warmup)
     lat.sync()
@@ -111,7 +112,8 @@ def cpu_baseline(N, target_s=12.0):
     from oracle import ref_c
     from paper_2512_23116_amd import params
     cfg = params.forced_hit(N)
-    lat = ref_c.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"])
+    lat = ref_c.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"],
+                        smag_form=cfg["smag_form"])
     f = lat.init(I.KIND_NOISE, cfg["noise"], cfg["init_seed"])
     t = time.perf_counter()
     f = lat.step(f, 2)
@@ -246,7 +248,7 @@ def main():
         "dtype": {"fp64": "f64"}.get(args.precision, "f32"),
         "data": "synthetic",
         "config": {
-            "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C=0.1 "
+            "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C_s=0.1 "
                          f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
                          f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
                          f"forcing, 1e-3 noise start, K_t stats every {args.diag_every} steps"),

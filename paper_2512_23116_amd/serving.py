@@ -68,7 +68,8 @@ class GpuEngine:
         F0 = params.forcing_amplitude(r.N)
         modes = random_solenoidal_modes(F0, r.force_seed)
         lat = self.lbm.Lattice((r.N, r.N, r.N), r.tau0, r.C, modes, precision="fp32",
-                               streaming="aa", steps_per_graph=self.G, stream=self.stream)
+                               streaming="aa", smag_form=params.SMAG_FORM,
+                               steps_per_graph=self.G, stream=self.stream)
         lat.init(self.lbm.LBM_INIT_NOISE, self.noise, r.init_seed)
         self.lat[r.rid] = lat
 

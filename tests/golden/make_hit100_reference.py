@@ -2,7 +2,7 @@
 
 Runs the C oracle (only ``oracle/`` and the seeded input generator are used)
 on the forced-HIT LES workload: 100^3 periodic, tau0 = 1/2 + 3 U0 N / Re with
-U0 = 0.043, Re = 2e4 (Sec. 3.1, Sec. 4), Smagorinsky C = 0.1 (linear form),
+U0 = 0.043, Re = 2e4 (Sec. 3.1, Sec. 4), nu_t = (C_s Delta)^2 |S| with C_s = 0.1,
 16-mode solenoidal forcing on |k| <= 2 with F0 = C_f U0^2 / N (eq.
 forcing_amplitude, C_f = 0.2), start from rest plus 1e-3 velocity noise.  Every
 500 steps up to 20000 it records the domain statistics of theta = tau_e - 1/2
@@ -35,6 +35,7 @@ from paper_2512_23116_amd.inputs import random_solenoidal_modes  # noqa: E402
 
 N = 100
 C_SMAG = 0.1
+SMAG_FORM = 1          # nu_t = (C_s Delta)^2 |S|
 NOISE, INIT_SEED, FORCE_SEED = 1e-3, 42, 1234
 KMAX = 25
 
@@ -63,7 +64,7 @@ def main():
     tau0 = P.tau0_from_re(U0, N, Re)
     F0 = P.forcing_amplitude(U0, N)
     modes = random_solenoidal_modes(F0, FORCE_SEED)
-    lat = ref_c.Lattice((N, N, N), tau0, C_SMAG, modes)
+    lat = ref_c.Lattice((N, N, N), tau0, C_SMAG, modes, smag_form=SMAG_FORM)
     f0 = lat.init(I.KIND_NOISE, NOISE, INIT_SEED)
     g0 = f0.copy()
     g0[0, 0, 0, 0] = np.nextafter(g0[0, 0, 0, 0], 1.0)       # one ulp
@@ -71,7 +72,7 @@ def main():
         _source=("FP64 C oracle, forced-HIT LES 100^3 (workload of this repository's benchmark); "
                  "written by tests/golden/make_hit100_reference.py, which calls only oracle/ "
                  "and the seeded forcing-table generator"),
-        N=N, tau0=tau0, C=C_SMAG, F0=F0, noise=NOISE, init_seed=INIT_SEED,
+        N=N, tau0=tau0, C=C_SMAG, smag_form=SMAG_FORM, F0=F0, noise=NOISE, init_seed=INIT_SEED,
         force_seed=FORCE_SEED, every=args.every, threads=ref_c.num_threads(),
         runs={"a": [], "b": []})
     for name, f in (("a", f0), ("b", g0)):

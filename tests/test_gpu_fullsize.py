@@ -60,12 +60,12 @@ def test_forced_hit_fullsize(lbm, orc, N):
     shape = (N, N, N)
     cfg = params.forced_hit(N)
     lat = lbm.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], precision="fp32",
-                      steps_per_graph=64)
+                      smag_form=cfg["smag_form"], steps_per_graph=64)
     lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
     st0 = lat.stats()
     lat.step(129)          # two graph replays and a plain launch (odd parity next)
     st1 = lat.stats()
-    olat = orc.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"])
+    olat = orc.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], smag_form=cfg["smag_form"])
     err = sampled_step_check(lat, olat, shape, _sample_cells(shape, 40, N))
     print(f"{N}^3: sampled one-step error {err:.3e}; mass drift "
           f"{abs(st1['mass'] - st0['mass']) / st0['mass']:.2e}", flush=True)
