@@ -105,6 +105,13 @@ typedef struct {
     int32_t n_force_modes;   /* 0..64                                         */
     int32_t steps_per_graph; /* steps captured per HIP graph in lbm_step
                                 (even, 2..1024); 0 disables graphs            */
+    int32_t temporal_block;  /* 0 or 1: one time step per pass over memory.
+                                2: pairs of steps run in one pass (A/B only,
+                                FP32/FP16/BF16; steps_per_graph a multiple of
+                                4 or 0): the intermediate level stays in LDS,
+                                halving HBM traffic per step at ~19% more
+                                arithmetic.  Same results as single steps.    */
+    int32_t reserved;        /* must be 0                                     */
     const lbm_force_mode* force_modes; /* copied at create                   */
     void* hip_stream;        /* hipStream_t to run on; NULL = null stream     */
     void* device_buffer;     /* optional caller-owned device memory for the
@@ -136,7 +143,7 @@ typedef struct {
 
 /* Fill *cfg with the paper's defaults: 32^3, FP32, AA, tau0 = 0.51, C = 0.1,
  * linear C, rho0 = 1, rates 1.19/1.4/1.2/1.4/1.98, no forcing, 64 steps per
- * graph, null stream, library-owned memory. */
+ * graph, one step per pass, null stream, library-owned memory. */
 void lbm_config_default(lbm_config* cfg);
 
 /* Bytes of device memory the population state needs: 19 direction planes per

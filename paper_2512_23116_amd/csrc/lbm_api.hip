@@ -104,6 +104,13 @@ bool validate(const lbm_config* c, std::string* why) {
     if (c->steps_per_graph != 0 &&
         (c->steps_per_graph < 2 || c->steps_per_graph > 1024 || (c->steps_per_graph & 1)))
         return bad("steps_per_graph must be 0 or even in [2, 1024]");
+    if (c->temporal_block < 0 || c->temporal_block > 2) return bad("temporal_block must be 0, 1 or 2");
+    if (c->reserved != 0) return bad("reserved must be 0");
+    if (c->temporal_block == 2) {
+        if (c->streaming != LBM_STREAM_AB) return bad("temporal_block 2 needs A/B streaming");
+        if (c->precision == LBM_FP64) return bad("temporal_block 2 needs 32- or 16-bit storage");
+        if (c->steps_per_graph % 4) return bad("temporal_block 2 needs steps_per_graph % 4 == 0");
+    }
     return true;
 }
 
@@ -141,10 +148,13 @@ lbm_status sync(lbm_handle* h) {
 
 lbm_status capture_graph(lbm_handle* h) {
     const int G = h->cfg.steps_per_graph;
+    const bool tb2 = h->cfg.temporal_block == 2;
     if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
-    // the graph starts from AA parity 0 / AB array 0 and, G being even, ends there
-    for (int k = 0; k < G; ++k) {
+    // the graph starts from AA parity 0 / AB array 0 and ends there (G even; G % 4 == 0
+    // for pairs of steps, whose launches alternate the arrays)
+    const int launches = tb2 ? G / 2 : G;
+    for (int k = 0; k < launches; ++k) {
         LatticeArgs a = h->args;
         int pat = PAT_AB;
         if (h->cfg.streaming == LBM_STREAM_AB) {
@@ -154,12 +164,13 @@ lbm_status capture_graph(lbm_handle* h) {
             a.a = a.b = h->state[0];
             pat = (k & 1) ? PAT_AA_ODD : PAT_AA_EVEN;
         }
-        hipError_t e = launch_step(h->cfg.precision, pat, a, h->cap_stream);
+        hipError_t e = tb2 ? launch_step_tb2(h->cfg.precision, a, h->cap_stream)
+                           : launch_step(h->cfg.precision, pat, a, h->cap_stream);
         if (e != hipSuccess) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h->cap_stream, &g);
             if (g) (void)hipGraphDestroy(g);
-            return hip_fail(h, e, "launch_step during capture");
+            return hip_fail(h, e, "launch during capture");
         }
     }
     HIPCHK(h, hipStreamEndCapture(h->cap_stream, &h->graph));
@@ -354,6 +365,7 @@ lbm_status lbm_step(lbm_handle* h, int64_t n) {
     if (n < 0) return fail(h, LBM_ERR_INVALID_ARG, "n must be >= 0");
     if (!h->initialized) return fail(h, LBM_ERR_STATE, "lbm_step before lbm_init_seeded/lbm_set_populations");
     const int G = h->cfg.steps_per_graph;
+    const bool tb2 = h->cfg.temporal_block == 2;
     while (n > 0) {
         const bool aligned = h->cfg.streaming == LBM_STREAM_AB ? (h->cur == 0) : ((h->steps & 1) == 0);
         if (G > 0 && n >= G && aligned) {
@@ -364,6 +376,12 @@ lbm_status lbm_step(lbm_handle* h, int64_t n) {
             HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
             h->steps += G;
             n -= G;
+        } else if (tb2 && n >= 2) {
+            hipError_t e = launch_step_tb2(h->cfg.precision, current_args(h), h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "two-step kernel");
+            h->steps += 2;
+            h->cur ^= 1;
+            n -= 2;
         } else {
             hipError_t e = launch_step(h->cfg.precision, current_pattern(h), current_args(h), h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "step kernel");

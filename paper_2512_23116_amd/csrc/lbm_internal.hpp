@@ -61,6 +61,9 @@ hipError_t launch_scatter_plane(int precision, int pat, const LatticeArgs& L, in
                                 const double* in, hipStream_t s);
 hipError_t launch_sample(int precision, int pat, const LatticeArgs& L, const int64_t* cells,
                          int64_t n, double* out, hipStream_t s);
+// Two steps in one pass (lbm_tb2.hip): A/B pull from L.a into L.b.
+bool tb2_supported(int precision);
+hipError_t launch_step_tb2(int precision, const LatticeArgs& L, hipStream_t s);
 
 constexpr int kDiagBlocks = 1024;   // fixed grid of the diagnostic reduction
 constexpr int kDiagSlots = 16;      // doubles per block partial

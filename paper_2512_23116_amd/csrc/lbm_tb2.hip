@@ -1,0 +1,192 @@
+// lbm_tb2.hip — two time steps per pass over HBM (A/B pull streaming).
+//
+// A single step moves 2 * 19 * b bytes per cell through HBM, and the
+// single-step kernel runs at the ceiling of that access pattern.  This kernel
+// keeps the intermediate time level on chip instead: a workgroup owns a
+// 62 x 14 tile of (x, y) columns plus a one-cell halo (64 x 16 = 1024
+// threads) and marches along z through a chunk of planes.
+//   phase 1  each of the 1024 columns pulls f(t) of plane z+1 from A
+//            (eq. mrt_dns_guo, periodic) and collides; of the post-collision
+//            values it keeps in LDS exactly what phase 2 will pull: the 5
+//            populations with c_z = -1 (needed now), the 9 with c_z = 0
+//            (needed one plane later, 2 slots) and the 5 with c_z = +1
+//            (needed two planes later, 3 slots): 38 floats per column,
+//            152 KB of the 160 KB LDS of a CDNA4 CU;
+//   phase 2  each interior column pulls the step-(t+1) populations of plane z
+//            from those buffers (planes z+1, z, z-1 and the neighbouring
+//            columns), collides and writes B at its own cell.
+// The loads of the next phase-1 plane are issued before phase 2 so that they
+// overlap with its arithmetic.  HBM traffic per two cell updates: A is read
+// once per extended column (1024 / 868 of the interior, plus 2 planes per
+// chunk) and B is written once, instead of two full reads and writes.
+// Per cell the arithmetic is the single-step collision; for 16-bit storage
+// the LDS buffers hold values rounded through the storage codec, so the
+// result matches two single steps.
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int TB_EX = 64, TB_EY = 16, TB_TX = TB_EX - 2, TB_TY = TB_EY - 2;
+constexpr int TB_E = TB_EX * TB_EY;
+
+// Position of direction i within its class of c_z (-1: 5, 0: 9, +1: 5).
+__host__ __device__ constexpr int zclass_index(int i) {
+    int n = 0;
+    for (int k = 0; k < i; ++k) n += (cz_of(k) == cz_of(i)) ? 1 : 0;
+    return n;
+}
+
+struct TB2Args {
+    LatticeArgs L;
+    uint32_t tiles_x, tiles_y, zchunk, nblocks;
+};
+
+template <class Cd>
+__device__ __forceinline__ typename Cd::R storage_round(typename Cd::R v, const LatticeArgs& L) {
+    using R = typename Cd::R;
+    if constexpr (std::is_same_v<typename Cd::T, R>) return v;
+    else return dec<Cd>(enc<Cd>(v, scale_of<R>(L)), inv_scale_of<R>(L));
+}
+
+__device__ __forceinline__ uint32_t wrap_add(uint32_t base, int d, uint32_t n) {
+    // (base + d) mod n for base < n and -1 <= d <= 64 (n >= 1)
+    int v = (int)base + d;
+    if (v < 0) v += (int)n;
+    return (uint32_t)v % n;
+}
+
+template <class Cd>
+__global__ __launch_bounds__(TB_E) void k_step_tb2(TB2Args A) {
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    static_assert(std::is_same_v<R, float>, "the LDS buffers hold FP32 values");
+    __shared__ R down[5][TB_E];      // c_z = -1 populations of plane z+1
+    __shared__ R mid[2][9][TB_E];    // c_z =  0 populations, planes z+1 and z
+    __shared__ R up[3][5][TB_E];     // c_z = +1 populations, planes z+1, z, z-1
+
+    const LatticeArgs& L = A.L;
+    uint32_t b = blockIdx.x;
+    if (L.xcd_remap) {
+        const uint32_t G = gridDim.x, xcd = b & 7u, local = b >> 3;
+        const uint32_t per = G >> 3, rem = G & 7u;
+        b = xcd * per + (xcd < rem ? xcd : rem) + local;
+    }
+    const uint32_t tile_x = b % A.tiles_x;
+    const uint32_t rest = b / A.tiles_x;
+    const uint32_t tile_y = rest % A.tiles_y;
+    const uint32_t zc = rest / A.tiles_y;
+    const uint32_t X0 = tile_x * TB_TX, Y0 = tile_y * TB_TY, Z0 = zc * A.zchunk;
+    const int nzc = (int)min(A.zchunk, L.nz - Z0);        // output planes of this chunk
+
+    const int t = threadIdx.x;
+    const int ex = t & (TB_EX - 1), ey = t / TB_EX;
+    // phase-1 column: the extended tile, wrapped onto the lattice
+    const uint32_t x1 = wrap_add(X0, ex - 1, L.nx), y1 = wrap_add(Y0, ey - 1, L.ny);
+    // phase-2 column: interior only, never wrapped
+    const uint32_t x2 = X0 + (uint32_t)ex - 1u, y2 = Y0 + (uint32_t)ey - 1u;
+    const bool inner = ex >= 1 && ex <= TB_TX && ey >= 1 && ey <= TB_TY && x2 < L.nx && y2 < L.ny;
+
+    const T* src = (const T*)L.a;
+    T* dst = (T*)L.b;
+    const R inv_s = inv_scale_of<R>(L), s_st = scale_of<R>(L);
+    const CollideConst<R>& k = collide_const<R>(L);
+
+    auto plane1 = [&](int j) {   // z of the phase-1 plane of iteration j: Z0 - 1 + j, wrapped
+        int z = (int)Z0 - 1 + j;
+        if (z < 0) z += (int)L.nz;
+        if (z >= (int)L.nz) z -= (int)L.nz;
+        return (uint32_t)z;
+    };
+    auto pull = [&](int j, R (&g)[19]) {
+        CellPos p;
+        p.x = x1;
+        p.y = y1;
+        p.z = plane1(j);
+        p.row = y1 + L.ny * p.z;
+        const Nbr nb = make_nbr(p, L);
+        load_cell<Cd, PAT_AB>(src, L.plane, x1 + L.nx * p.row, nb, g, inv_s);
+    };
+
+    R pre[19];
+    pull(0, pre);
+    for (int j = 0; j < nzc + 2; ++j) {
+        {   // phase 1: step t at plane Z0 - 1 + j for every extended column
+            R g[19];
+#pragma unroll
+            for (int i = 0; i < 19; ++i) g[i] = pre[i];
+            CellPos p;
+            p.x = x1;
+            p.y = y1;
+            p.z = plane1(j);
+            p.row = y1 + L.ny * p.z;
+            R Fx, Fy, Fz;
+            force_at<R>(L, p, Fx, Fy, Fz);
+            collide<R, true>(g, Fx, Fy, Fz, k);
+            const int s2 = j & 1, s3 = j % 3;
+            static_for<19>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cz = cz_of(i), ii = zclass_index(i);
+                const R v = storage_round<Cd>(g[i], L);
+                if constexpr (cz < 0) down[ii][t] = v;
+                else if constexpr (cz == 0) mid[s2][ii][t] = v;
+                else up[s3][ii][t] = v;
+            });
+        }
+        __syncthreads();
+        if (j + 1 < nzc + 2) pull(j + 1, pre);
+        if (j >= 2 && inner) {   // phase 2: step t+1 at plane Z0 + j - 2
+            const uint32_t z2 = Z0 + (uint32_t)(j - 2);
+            R g[19];
+            const int s2 = (j - 1) & 1, s3 = (j - 2) % 3;   // planes z2 and z2 - 1
+            static_for<19>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i), ii = zclass_index(i);
+                const int col = (ex - cx) + TB_EX * (ey - cy);
+                if constexpr (cz < 0) g[i] = down[ii][col];          // from plane z2 + 1
+                else if constexpr (cz == 0) g[i] = mid[s2][ii][col]; // from plane z2
+                else g[i] = up[s3][ii][col];                         // from plane z2 - 1
+            });
+            CellPos p;
+            p.x = x2;
+            p.y = y2;
+            p.z = z2;
+            p.row = y2 + L.ny * z2;
+            R Fx, Fy, Fz;
+            force_at<R>(L, p, Fx, Fy, Fz);
+            collide<R, true>(g, Fx, Fy, Fz, k);
+            const uint32_t cell = x2 + L.nx * p.row;
+            static_for<19>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                *elem_ptr(dst, i, L.plane, cell) = enc<Cd>(g[i], s_st);
+            });
+        }
+        __syncthreads();
+    }
+}
+
+bool tb2_supported(int precision) { return precision != LBM_FP64; }
+
+hipError_t launch_step_tb2(int precision, const LatticeArgs& L, hipStream_t s) {
+    TB2Args A;
+    A.L = L;
+    A.tiles_x = (L.nx + TB_TX - 1) / TB_TX;
+    A.tiles_y = (L.ny + TB_TY - 1) / TB_TY;
+    // enough workgroups (one per CU at a time) to fill 256 CUs several times
+    // over, but long z chunks
+    const uint32_t tiles = A.tiles_x * A.tiles_y;
+    uint32_t chunks = (2048 + tiles - 1) / tiles;
+    chunks = std::max(1u, std::min(chunks, std::max(1u, L.nz / 16)));
+    A.zchunk = (L.nz + chunks - 1) / chunks;
+    chunks = (L.nz + A.zchunk - 1) / A.zchunk;
+    A.nblocks = tiles * chunks;
+    const dim3 grid(A.nblocks), block(TB_E);
+    switch (precision) {
+        case LBM_FP32: hipLaunchKernelGGL(k_step_tb2<CdF32>, grid, block, 0, s, A); break;
+        case LBM_FP16_DEV: hipLaunchKernelGGL(k_step_tb2<CdF16>, grid, block, 0, s, A); break;
+        case LBM_BF16_DEV: hipLaunchKernelGGL(k_step_tb2<CdBF16>, grid, block, 0, s, A); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm
