@@ -194,6 +194,24 @@ lbm_status lbm_set_populations(lbm_handle* h, const double* f);
  * cells[i] (0 <= cells[i] < ncells).  Host arrays.  Synchronises. */
 lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n, double* out);
 
+/* Shell-binned kinetic-energy spectrum of the current state (Sec. 2.2,
+ * eq. integral_length_scale with the squared modulus):
+ *   E[k] = 1/2 sum_{k - 1/2 <= |q| < k + 1/2} |u_hat(q)|^2,  u_hat = FFT(u) / ncells,
+ * for integer shells k = 0..kmax (0 <= kmax <= 4096), u the velocity with the
+ * half-force shift of eq. guo_velocity.  FP64 FFT (hipFFT) on the device; the
+ * shell sums use LDS atomics, so the last bits may vary between calls.  Host
+ * double[kmax+1].  Allocates device temporaries (~ncells * 40 bytes).
+ * Synchronises. */
+lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
+
+/* Longitudinal structure functions of the current state (Sec. 5.3): for each
+ * separation rs[j] >= 1 (taken modulo the lattice size per axis),
+ *   out[6 j + m] = mean over cells x and axes a of p_m(du),
+ *   du = u_a(x + r e_a) - u_a(x) (periodic),  p = (du^2, du^3, |du|^3, du^4, |du|^5, du^6).
+ * F4(r) = out[6j+3] / out[6j]^2.  FP64, reduced in a fixed order (bitwise
+ * reproducible).  nr in 1..65535.  Allocates device temporaries.  Synchronises. */
+lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr, double* out);
+
 /* Checkpoint / resume in the storage format: lbm_state_bytes() bytes of
  * opaque state (host memory) plus the step count.  Restoring into a handle
  * created with the same config reproduces the run bitwise.  Both synchronise.

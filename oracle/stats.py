@@ -48,3 +48,28 @@ def energy_spectrum(u):
     kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
     shell = np.floor(kmag + 0.5).astype(np.int64)
     return np.bincount(shell.ravel(), weights=e.ravel())
+
+
+SF_ORDERS = ("S2", "S3", "S3abs", "S4", "S5abs", "S6")
+
+
+def structure_functions(u, rs):
+    """Longitudinal structure functions averaged over the three axes.
+
+    Sec. 2.2 / 5.3 use increments of the velocity component along the
+    separation: du_a(x; r) = u_a(x + r e_a) - u_a(x), periodic.  Returns an
+    array (len(rs), 6) of <du^2>, <du^3>, <|du|^3>, <du^4>, <|du|^5>, <du^6>,
+    each averaged over all cells and the three axes.  F4(r) = S4 / S2^2.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros((len(rs), 6))
+    axis_of = {0: 2, 1: 1, 2: 0}          # component x varies along array axis 2, ...
+    for j, r in enumerate(rs):
+        acc = np.zeros(6)
+        for a in range(3):
+            du = np.roll(u[a], -r, axis=axis_of[a]) - u[a]
+            d2 = du * du
+            acc += [d2.mean(), (d2 * du).mean(), (d2 * np.abs(du)).mean(), (d2 * d2).mean(),
+                    (d2 * d2 * np.abs(du)).mean(), (d2 * d2 * d2).mean()]
+        out[j] = acc / 3.0
+    return out

@@ -1,0 +1,223 @@
+// lbm_analysis.hip — on-device turbulence diagnostics of the current state:
+// the shell-binned kinetic-energy spectrum (Sec. 2.2, eq. integral_length_scale
+// with the squared modulus) and longitudinal structure functions / flatness
+// (Sec. 5.3).  Both start from the velocity with the half-force shift
+// (eq. guo_velocity) that lbm_moments returns, computed on the device in FP64.
+#include <hipfft/hipfft.h>
+
+#include <algorithm>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int kAnaBlocks = 1024;
+
+// Per-block partial sums of 1/2 w |c|^2 / n^2 over the shells 0..kmax of one
+// R2C output c[nz][ny][nx/2+1]; w = 2 for the kx > 0 modes that stand for a
+// conjugate pair.
+__global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c, uint32_t nx,
+                                                   uint32_t ny, uint32_t nz, int kmax,
+                                                   double inv_n2, double* partials) {
+    extern __shared__ double hist[];
+    for (int k = threadIdx.x; k <= kmax; k += 256) hist[k] = 0.0;
+    __syncthreads();
+    const uint32_t hx = nx / 2 + 1;
+    const uint64_t total = (uint64_t)hx * ny * nz;
+    for (uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x; m < total;
+         m += (uint64_t)gridDim.x * 256) {
+        const uint32_t ix = (uint32_t)(m % hx);
+        const uint64_t r = m / hx;
+        const uint32_t iy = (uint32_t)(r % ny), iz = (uint32_t)(r / ny);
+        const double kx = ix;
+        const double ky = iy <= ny / 2 ? (double)iy : (double)iy - ny;
+        const double kz = iz <= nz / 2 ? (double)iz : (double)iz - nz;
+        const int shell = (int)floor(sqrt(kx * kx + ky * ky + kz * kz) + 0.5);
+        if (shell > kmax) continue;
+        const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
+        const hipfftDoubleComplex v = c[m];
+        atomicAdd(&hist[shell], 0.5 * w * (v.x * v.x + v.y * v.y) * inv_n2);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= kmax; k += 256)
+        partials[(uint64_t)blockIdx.x * (kmax + 1) + k] = hist[k];
+}
+
+// out[j] (+)= sum over rows b of partials[b][j], fixed order, one thread per column.
+__global__ __launch_bounds__(256) void k_sum_rows(const double* partials, int rows, int cols,
+                                                  double scale, int accumulate, double* out) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int b = 0; b < rows; ++b) s += partials[(uint64_t)b * cols + j];
+    out[j] = accumulate ? out[j] + s * scale : s * scale;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// Per-block sums of du^2, du^3, |du|^3, du^4, |du|^5, du^6 for the separation
+// rs[blockIdx.y] along each axis, du = u_a(x + r e_a) - u_a(x), periodic.
+__global__ __launch_bounds__(256) void k_structure(const double* u, uint32_t nx, uint32_t ny,
+                                                   uint32_t nz, const int32_t* rs, double* partials) {
+    __shared__ double red[4];
+    const uint32_t r = (uint32_t)rs[blockIdx.y];
+    const uint32_t rx = r % nx, ry = r % ny, rz = r % nz;
+    const uint64_t ncell = (uint64_t)nx * ny * nz;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < ncell;
+         c += (uint64_t)gridDim.x * 256) {
+        const uint32_t x = (uint32_t)(c % nx);
+        const uint64_t row = c / nx;
+        const uint32_t y = (uint32_t)(row % ny), z = (uint32_t)(row / ny);
+        const uint32_t xs = x + rx >= nx ? x + rx - nx : x + rx;
+        const uint32_t ys = y + ry >= ny ? y + ry - ny : y + ry;
+        const uint32_t zs = z + rz >= nz ? z + rz - nz : z + rz;
+        const uint64_t c_x = (uint64_t)xs + (uint64_t)nx * row;
+        const uint64_t c_y = x + (uint64_t)nx * (ys + (uint64_t)ny * z);
+        const uint64_t c_z = x + (uint64_t)nx * (y + (uint64_t)ny * zs);
+        const double d[3] = {u[c_x] - u[c], u[ncell + c_y] - u[ncell + c],
+                             u[2 * ncell + c_z] - u[2 * ncell + c]};
+        for (int a = 0; a < 3; ++a) {
+            const double du = d[a], d2 = du * du, ad = fabs(du);
+            acc[0] += d2;
+            acc[1] += d2 * du;
+            acc[2] += d2 * ad;
+            acc[3] += d2 * d2;
+            acc[4] += d2 * d2 * ad;
+            acc[5] += d2 * d2 * d2;
+        }
+    }
+    for (int m = 0; m < 6; ++m) {
+        const double s = block_sum(acc[m], red);
+        if (threadIdx.x == 0)
+            partials[((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * 6 + m] = s;
+    }
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+const char* fft_error(hipfftResult r) {
+    switch (r) {
+        case HIPFFT_SUCCESS: return "success";
+        case HIPFFT_ALLOC_FAILED: return "allocation failed";
+        case HIPFFT_INVALID_VALUE: return "invalid value";
+        case HIPFFT_INVALID_SIZE: return "invalid size";
+        default: return "hipFFT error";
+    }
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+lbm_status set_err(lbm_handle* h, lbm_status st, const std::string& m) {
+    h->err = m;
+    return st;
+}
+
+lbm_status hip_err(lbm_handle* h, hipError_t e, const char* what) {
+    return set_err(h, e == hipErrorOutOfMemory ? LBM_ERR_OUT_OF_MEMORY : LBM_ERR_DEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Velocity (FP64, [3][ncell]) of the current state into a new device buffer.
+lbm_status velocity(lbm_handle* h, DevBuf& u) {
+    const size_t nc = h->args.ncell;
+    hipError_t e = hipMalloc(&u.p, 3 * nc * sizeof(double));
+    if (e != hipSuccess) return hip_err(h, e, "hipMalloc(velocity)");
+    e = launch_moments(h->cfg.precision, current_pattern(h), current_args(h), nullptr,
+                       (double*)u.p, h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "moments kernel");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (!E || kmax < 0 || kmax > 4096) return set_err(h, LBM_ERR_INVALID_ARG, "kmax must be 0..4096");
+    if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
+    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
+    const size_t nc = h->args.ncell, hx = nx / 2 + 1, nmodes = hx * (size_t)ny * nz;
+    DevBuf u, c, part, out;
+    lbm_status st = velocity(h, u);
+    if (st != LBM_OK) return st;
+    hipError_t e = hipMalloc(&c.p, nmodes * sizeof(hipfftDoubleComplex));
+    if (e == hipSuccess) e = hipMalloc(&part.p, (size_t)kAnaBlocks * (kmax + 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&out.p, (size_t)(kmax + 1) * sizeof(double));
+    if (e != hipSuccess) return hip_err(h, e, "hipMalloc(spectrum)");
+    hipfftHandle plan;
+    hipfftResult fr = hipfftPlan3d(&plan, (int)nz, (int)ny, (int)nx, HIPFFT_D2Z);
+    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
+    fr = hipfftSetStream(plan, h->stream);
+    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
+    const size_t shm = (size_t)(kmax + 1) * sizeof(double);
+    for (int a = 0; a < 3 && fr == HIPFFT_SUCCESS; ++a) {
+        fr = hipfftExecD2Z(plan, (hipfftDoubleReal*)u.p + (size_t)a * nc, (hipfftDoubleComplex*)c.p);
+        if (fr != HIPFFT_SUCCESS) break;
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
+                           (const hipfftDoubleComplex*)c.p, nx, ny, nz, (int)kmax, inv_n2,
+                           (double*)part.p);
+        hipLaunchKernelGGL(k_sum_rows, dim3((kmax + 1 + 255) / 256), dim3(256), 0, h->stream,
+                           (const double*)part.p, kAnaBlocks, (int)(kmax + 1), 1.0, a > 0,
+                           (double*)out.p);
+    }
+    (void)hipfftDestroy(plan);
+    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(E, out.p, shm, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "spectrum");
+    return LBM_OK;
+}
+
+lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr, double* out) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (nr < 1 || nr > 65535 || !rs || !out) return set_err(h, LBM_ERR_INVALID_ARG, "bad rs/nr/out");
+    for (int j = 0; j < nr; ++j)
+        if (rs[j] < 1) return set_err(h, LBM_ERR_INVALID_ARG, "separations must be >= 1");
+    if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
+    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
+    const size_t nc = h->args.ncell;
+    DevBuf u, drs, part, res;
+    lbm_status st = velocity(h, u);
+    if (st != LBM_OK) return st;
+    const int nb = (int)std::min<size_t>(kAnaBlocks, (nc + 255) / 256);
+    hipError_t e = hipMalloc(&drs.p, nr * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&part.p, (size_t)nr * nb * 6 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&res.p, (size_t)nr * 6 * sizeof(double));
+    if (e != hipSuccess) return hip_err(h, e, "hipMalloc(structure functions)");
+    e = hipMemcpyAsync(drs.p, rs, nr * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "copy separations");
+    hipLaunchKernelGGL(k_structure, dim3(nb, nr), dim3(256), 0, h->stream, (const double*)u.p, nx,
+                       ny, nz, (const int32_t*)drs.p, (double*)part.p);
+    // rows of 6 sums per (r, block): reduce blocks in a fixed order per r
+    for (int j = 0; j < nr; ++j)
+        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, h->stream,
+                           (const double*)part.p + (size_t)j * nb * 6, nb, 6, 1.0 / (3.0 * nc), 0,
+                           (double*)res.p + (size_t)j * 6);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, res.p, (size_t)nr * 6 * sizeof(double),
+                                            hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "structure functions");
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -34,6 +34,7 @@ EXPORTS = (
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
+    "lbm_spectrum", "lbm_structure_functions",
 )
 
 
@@ -115,6 +116,9 @@ def lib():
         "lbm_sample_populations": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int64),
                                                   ctypes.c_int64, dp]),
         "lbm_synchronize": (ctypes.c_int, [H]),
+        "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
+        "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
+                                                   ctypes.c_int32, dp]),
         "lbm_state_bytes": (ctypes.c_size_t, [H]),
         "lbm_save_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -233,6 +237,20 @@ def lbm_load_state(h, buf, steps):
     _check(lib().lbm_load_state(h, buf.ctypes.data, buf.size, steps), h)
 
 
+def lbm_spectrum(h, kmax):
+    E = np.empty(kmax + 1)
+    _check(lib().lbm_spectrum(h, kmax, _dp(E)), h)
+    return E
+
+
+def lbm_structure_functions(h, rs):
+    rs = np.ascontiguousarray(rs, dtype=np.int32)
+    out = np.empty((len(rs), 6))
+    _check(lib().lbm_structure_functions(
+        h, rs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(rs), _dp(out)), h)
+    return out
+
+
 def lbm_synchronize(h):
     _check(lib().lbm_synchronize(h), h)
 
@@ -346,6 +364,12 @@ class Lattice:
 
     def kt_field(self):
         return lbm_kt_field(self.handle, self.ncell).reshape(self.shape)
+
+    def spectrum(self, kmax):
+        return lbm_spectrum(self.handle, kmax)
+
+    def structure_functions(self, rs):
+        return lbm_structure_functions(self.handle, rs)
 
     def save(self):
         return lbm_save_state(self.handle)

@@ -454,3 +454,25 @@ def test_energy_spectrum_parseval_and_shell():
     v[0] = np.sin(2 * np.pi * 3 * x / N).reshape(1, 1, N)   # |k| = 3, energy 1/4
     E = ST.energy_spectrum(v)
     assert abs(E[3] - 0.25) < 1e-14 and abs(E.sum() - 0.25) < 1e-14
+
+
+def test_structure_functions_of_a_single_wave():
+    """u = (A sin(2 pi k x / N), 0, 0): along x, du = 2A cos(.) sin(pi k r / N), so
+    <du^2> = 2 A^2 s^2, <du^4> = 6 A^4 s^4, <du^6> = 20 A^6 s^6 (s = sin(pi k r/N)),
+    odd signed moments vanish; the y and z axes contribute nothing (1/3 weight)."""
+    N, k, A = 32, 3, 0.7
+    x = np.arange(N)
+    u = np.zeros((3, 4, 5, N))
+    u[0] = (A * np.sin(2 * np.pi * k * x / N)).reshape(1, 1, N)
+    rs = [1, 2, 5, 16]
+    S = ST.structure_functions(u, rs)
+    for j, r in enumerate(rs):
+        s = np.sin(np.pi * k * r / N)
+        np.testing.assert_allclose(S[j, 0], 2 * A ** 2 * s ** 2 / 3, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(S[j, 3], 6 * A ** 4 * s ** 4 / 3, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(S[j, 5], 20 * A ** 6 * s ** 6 / 3, rtol=1e-12, atol=1e-15)
+        assert abs(S[j, 1]) < 1e-15
+    # a transverse wave (u_x varying along y) has no longitudinal increments
+    v = np.zeros((3, 4, N, 5))
+    v[0] = (A * np.sin(2 * np.pi * k * x / N)).reshape(1, N, 1)
+    assert np.abs(ST.structure_functions(v, rs)).max() < 1e-15
