@@ -32,7 +32,7 @@ def _cell(x, y, z, shape):
     return (x % nx) + nx * ((y % ny) + ny * (z % nz))
 
 
-def sampled_step_check(lat, olat, shape, pts):
+def sampled_step_check(lat, olat, shape, pts, precision="fp32"):
     """f_i(x, n+1) from the GPU against the oracle's collision of the cell
     x - c_i at step n, for every sampled x and every i."""
     nbr = []
@@ -76,4 +76,20 @@ def test_forced_hit_fullsize(lbm, orc, N):
     lat.step(1)
     err = sampled_step_check(lat, olat, shape, _sample_cells(shape, 40, N + 1))
     assert err <= 1e-5
+    lat.close()
+
+
+def test_fp64_256_one_step_sampled(lbm, orc):
+    """256^3 in FP64 (A/B, 2.5 GB per array): sampled one-step error <= 1e-12."""
+    N = 256
+    shape = (N, N, N)
+    cfg = params.forced_hit(N)
+    lat = lbm.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], precision="fp64", streaming="ab",
+                      smag_form=cfg["smag_form"])
+    lat.init(lbm.LBM_INIT_NOISE, 0.02, cfg["init_seed"])
+    lat.step(65)
+    olat = orc.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], smag_form=cfg["smag_form"])
+    err = sampled_step_check(lat, olat, shape, _sample_cells(shape, 30, 7))
+    print(f"256^3 fp64: sampled one-step error {err:.3e}", flush=True)
+    assert err <= 1e-12
     lat.close()
