@@ -16,8 +16,6 @@ on the kernel's stream), the 800^3 FP32 AA run, the batched-serving run
 on the host cores on a bounded sample.
 """
 import argparse
-import hashlib
-import glob
 import json
 import os
 import sys
@@ -35,21 +33,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2512_23116_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-def counter_traffic(workload_key):
+def counter_traffic(workload_key, family="k_step"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources (else None)."""
+    taken on the current sources of that kernel (else None)."""
+    from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    sha = kernel_source_sha()
+    sha = kernel_source_sha(family)
     for line in open(path):
         parts = line.split()
         if len(parts) >= 5 and not line.startswith("#") and parts[0] == workload_key \
@@ -160,11 +151,13 @@ def profile_run(lbm, params, args):
     del x, y
     torch.cuda.empty_cache()
     log("profile: 3 copies of 1 GiB done")
-    for N, steps in ((args.N, 8), (args.large_N, 4)):
-        if N == args.large_N and args.no_large:
-            continue
-        run_lattice(lbm, params, N, args.precision, args.streaming, steps, 2, 0, spg=0)
-        log(f"profile: {N}^3 {args.precision} {args.streaming}, {steps} plain launches done")
+    runs = [(args.N, args.streaming, 0, 8)]
+    if not args.no_large:
+        runs += [(args.large_N, "aa", 0, 4), (args.large_N, "ab", 0, 4), (args.large_N, "ab", 2, 8)]
+    for N, streaming, tb, steps in runs:
+        run_lattice(lbm, params, N, args.precision, streaming, steps, 2, 0, spg=0, tb=tb)
+        log(f"profile: {N}^3 {args.precision} {streaming}{' two-step' if tb else ''}, "
+            f"{steps} steps of plain launches done")
 
 
 def main():
@@ -293,18 +286,27 @@ def main():
                            "ms_per_step": round(large_ab["ms_per_step"], 4),
                            "roofline": {"bound": "hbm", "achieved": round(lr["achieved"], 1),
                                         "peak": lr["peak"], "unit": "GB/s",
-                                        "frac": round(lr["frac"], 4)}}
+                                        "frac": round(lr["frac"], 4),
+                                        "traffic": counter_traffic(f"{args.large_N}_fp32_ab")}}
     if large_tb2:
         lr = large_tb2["roofline"]
+        # one launch = one pass = two time steps; its algorithmic bytes are one read
+        # and one write of every population, the same as a single step's
+        pass_us = 2 * large_tb2["avg_launch_us"]
+        own = lr["bytes_per_launch"] / (pass_us * 1e-6) / 1e9
         out["large_tb2"] = {
             "workload": (f"forced HIT LES {args.large_N}^3 fp32 A/B, two time steps per pass "
                          "(intermediate level in LDS)"),
             "mlups": round(large_tb2["mlups"], 1), "steps": large_tb2["steps"],
             "ms_per_step": round(large_tb2["ms_per_step"], 4),
-            "roofline": {"bound": "hbm", "achieved": round(lr["achieved"], 1), "peak": lr["peak"],
-                         "unit": "GB/s", "frac": round(lr["frac"], 4),
-                         "note": "achieved = 2*19*4 B per cell update / time: the single-step "
-                                 "algorithmic bytes; the kernel itself moves ~60% of them"}}
+            "roofline": {"bound": "hbm", "achieved": round(own, 1), "peak": lr["peak"],
+                         "unit": "GB/s", "frac": round(own / lr["peak"], 4),
+                         "traffic": counter_traffic(f"{args.large_N}_fp32_ab_tb2", "k_step_tb2"),
+                         "avg_launch_us": round(pass_us, 3)},
+            "step_equivalent": {
+                "achieved": round(lr["achieved"], 1), "frac": round(lr["frac"], 4),
+                "note": "2*19*4 B per cell update / time: the bytes a one-step-per-pass "
+                        "kernel must move for the same MLUPS"}}
     if serving:
         out["serving"] = serving
     print(json.dumps(out), flush=True)

@@ -13,7 +13,8 @@ with a known-size copy kernel; the counters' reading for it calibrates the
 counters to bytes (FETCH_SIZE reads half of the true bytes on MI355X), and the
 calibrated bytes per step launch are compared with the algorithmic 2*19*b*N^3.
 With ``--traffic-out`` one line per lattice is appended for bench.py:
-``<N>_<precision>_<streaming> <kernel-source sha> <fetch bytes> <write bytes>``.
+``<N>_<precision>_<streaming>[_tb2] <kernel-source sha> <fetch bytes> <write bytes>``,
+the sha taken over the sources that kernel is compiled from (KERNEL_SOURCES).
 """
 import argparse
 import collections
@@ -27,12 +28,39 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
-def kernel_source_sha():
+# Sources each step kernel is compiled from: its counters stay valid while these
+# files are unchanged.
+_COMMON = ("d3q19_mrt.hpp", "lbm_device.hpp", "lbm_internal.hpp")
+KERNEL_SOURCES = {
+    "k_step": ("lbm_kernels.hip",) + _COMMON,
+    "k_step_tb2": ("lbm_tb2.hip",) + _COMMON,
+}
+
+
+def kernel_source_sha(family="k_step"):
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in KERNEL_SOURCES[family]:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(os.path.dirname(HERE), "include", "lbm.h"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def lattice_key(kernel, grid, precision, tb2_n):
+    """(family, traffic key) of a step-kernel launch, or None for other kernels.
+
+    k_step launches one thread per cell (grid = N^3 rounded up to 256); the
+    pattern template argument tells AA (0, 1) from A/B (2).  The two-step kernel's
+    grid counts tiles, so its lattice edge is given (tb2_n)."""
+    k = short(kernel)
+    if k.startswith("k_step_tb2"):
+        return "k_step_tb2", f"{tb2_n}_{precision}_ab_tb2"
+    if not k.startswith("k_step<"):
+        return None
+    pattern = k.split(",")[1].strip()
+    N = round(grid ** (1 / 3))
+    return "k_step", f"{N}_{precision}_{'ab' if pattern == '2' else 'aa'}"
 
 
 def _csv(d, suffix):
@@ -85,11 +113,15 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--streaming", default="aa")
     ap.add_argument("--traffic-out")
+    ap.add_argument("--tb2-n", type=int, default=800,
+                    help="lattice edge of the two-step kernel launches in the counter runs")
     a = ap.parse_args()
     b = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[a.precision]
     if a.cmd:
         print(f"command: {a.cmd}")
-    print(f"kernel sources sha256[:16]: {kernel_source_sha()}")
+    for fam in KERNEL_SOURCES:
+        print(f"{fam} sources ({', '.join(KERNEL_SOURCES[fam])}, lbm.h) sha256[:16]: "
+              f"{kernel_source_sha(fam)}")
     if a.trace:
         print("\nkernel trace (durations in us; grid = threads launched)")
         print(f"{'kernel':58s} {'grid':>11s} {'calls':>6s} {'mean':>10s} {'median':>10s} "
@@ -103,29 +135,30 @@ def main():
         wcal = COPY_BYTES / 1024 / calibration(wb)
         print(f"\ncounter calibration on a 1 GiB copy: FETCH_SIZE x {fcal:.4f}, "
               f"WRITE_SIZE x {wcal:.4f}")
-        print(f"{'kernel':58s} {'cells':>11s} {'fetch GB':>9s} {'write GB':>9s} "
-              f"{'alg GB':>8s} {'ratio':>6s}")
-        per_lattice = collections.defaultdict(lambda: [0.0, 0.0, 0])
+        print(f"{'kernel':40s} {'lattice':>16s} {'fetch GB':>9s} {'write GB':>9s} "
+              f"{'step alg GB':>11s} {'ratio':>6s}")
+        per_key = collections.defaultdict(lambda: [0.0, 0.0, 0, ""])
         for (k, g), v in sorted(fb.items()):
-            if "k_step" not in k:
+            lk = lattice_key(k, g, a.precision, a.tb2_n)
+            if lk is None:
                 continue
+            fam, key = lk
+            N = int(key.split("_")[0])
             f = statistics.mean(v) * 1024 * fcal
             w = statistics.mean(wb[(k, g)]) * 1024 * wcal
-            cells = round(g ** (1 / 3)) ** 3     # the grid is rounded up to whole blocks
-            alg = 2 * 19 * b * cells
-            print(f"{short(k)[:58]:58s} {cells:11d} {f / 1e9:9.4f} {w / 1e9:9.4f} {alg / 1e9:8.4f} "
+            alg = 2 * 19 * b * N ** 3      # one read and one write of every population
+            print(f"{short(k)[:40]:40s} {key:>16s} {f / 1e9:9.4f} {w / 1e9:9.4f} {alg / 1e9:11.4f} "
                   f"{(f + w) / alg:6.3f}")
-            acc = per_lattice[g]
+            acc = per_key[key]
             acc[0] += f
             acc[1] += w
             acc[2] += 1
+            acc[3] = fam
         if a.traffic_out:
-            sha = kernel_source_sha()
             with open(a.traffic_out, "a") as fh:
-                for g, (f, w, n) in sorted(per_lattice.items()):
-                    N = round(g ** (1 / 3))
-                    fh.write(f"{N}_{a.precision}_{a.streaming} {sha} {f / n:.6e} {w / n:.6e} "
-                             f"k_step mean over {n} kernels\n")
+                for key, (f, w, n, fam) in sorted(per_key.items()):
+                    fh.write(f"{key} {kernel_source_sha(fam)} {f / n:.6e} {w / n:.6e} "
+                             f"{fam} mean over {n} kernels\n")
 
 
 if __name__ == "__main__":
