@@ -111,7 +111,15 @@ typedef struct {
                                 4 or 0): the intermediate level stays in LDS,
                                 halving HBM traffic per step at ~19% more
                                 arithmetic.  Same results as single steps.    */
-    int32_t reserved;        /* must be 0                                     */
+    int32_t tau_mode;        /* which relaxation rate enters the strain
+                                estimate of App. B.1 eq. yu_strain:
+                                0: s_1 = s_e and s_9 = 1/tau0 (explicit,
+                                   default);
+                                1: self-consistent s_9 = 1/tau_e with the
+                                   s_1 (divergence) term dropped, solved in
+                                   closed form: tau_e = (tau0 + sqrt(tau0^2
+                                   + 4 c3 |S_1|)) / 2, S_1 = eq. yu_strain at
+                                   s_1 = 0, s_9 = 1, c3 = 3 C or 3 C^2.      */
     const lbm_force_mode* force_modes; /* copied at create                   */
     void* hip_stream;        /* hipStream_t to run on; NULL = null stream     */
     void* device_buffer;     /* optional caller-owned device memory for the

@@ -36,7 +36,7 @@ class _Params(ctypes.Structure):
         ("tau0", ctypes.c_double), ("C", ctypes.c_double), ("rho0", ctypes.c_double),
         ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
         ("s_pi", ctypes.c_double), ("s_m", ctypes.c_double),
-        ("n_modes", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("n_modes", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
         ("mode_k", ctypes.POINTER(ctypes.c_int32)),
         ("mode_amp", ctypes.POINTER(ctypes.c_double)),
         ("mode_phase", ctypes.POINTER(ctypes.c_double)),
@@ -81,7 +81,7 @@ class Lattice:
     """Parameters of one oracle lattice; keeps the mode arrays alive."""
 
     def __init__(self, shape, tau0, C, modes=(), smag_form=0, rho0=1.0,
-                 s_e=L.S_E, s_eps=L.S_EPS, s_q=L.S_Q, s_pi=L.S_PI, s_m=L.S_M):
+                 s_e=L.S_E, s_eps=L.S_EPS, s_q=L.S_Q, s_pi=L.S_PI, s_m=L.S_M, tau_mode=0):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
         modes = list(modes)
@@ -92,7 +92,7 @@ class Lattice:
             np.array([m[1] for m in modes], dtype=np.float64).reshape(n, 3))
         self._ph = np.ascontiguousarray(np.array([m[2] for m in modes], dtype=np.float64))
         self.p = _Params(nx, ny, nz, smag_form, tau0, C, rho0, s_e, s_eps, s_q, s_pi, s_m,
-                         n, 0,
+                         n, tau_mode,
                          self._k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          self._amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))

@@ -16,8 +16,10 @@
  *   f* = M^-1 m*,  f(x + c, t+1) = f*(x, t)          App. A eq. mrt_dns_guo
  * Readings (also in the numpy definition): the printed m_eq is for deviation
  * populations, so the rest-state moments rho0 (1, -11, 3, 0, ...) are added
- * for full populations; s_1 = s_e and s_9 = 1/tau0 enter eq. yu_strain; the
- * constant C enters nu_t linearly unless smag_form = 1 (C^2).
+ * for full populations; s_1 = s_e and s_9 = 1/tau0 enter eq. yu_strain
+ * (tau_mode 0), or, self-consistently, the s_1 term is dropped and s_9 = 1/tau_e
+ * (tau_mode 1, solved in closed form); the constant C enters nu_t linearly
+ * unless smag_form = 1 (C^2).
  *
  * Data: full populations f[a][z][y][x], x fastest, a in the order of
  * App. B Fig. d3q19_table (0-based, rest last).
@@ -70,7 +72,8 @@ typedef struct {
     int32_t nx, ny, nz, smag_form;
     double tau0, C, rho0;
     double s_e, s_eps, s_q, s_pi, s_m; /* eq. relaxation-matrix fixed rates */
-    int32_t n_modes, pad;
+    int32_t n_modes;
+    int32_t tau_mode;          /* 0: s_9 = 1/tau0 in eq. yu_strain; 1: self-consistent */
     const int32_t* mode_k;     /* [n_modes][3] */
     const double* mode_amp;    /* [n_modes][3] */
     const double* mode_phase;  /* [n_modes]    */
@@ -115,6 +118,19 @@ void orc_force_at(const orc_params* p, int x, int y, int z, double F[3]) {
         double s = sin(arg);
         for (int a = 0; a < 3; ++a) F[a] += p->mode_amp[3 * m + a] * s;
     }
+}
+
+/* |S| of eq. strain_norm from the strain rate of eq. yu_strain (delta_t = 1)
+ * with relaxation rates s1 (row 1) and s9 (rows 9, 11, 13-15). */
+static double strain_norm_of(const double mneq[Q], double s1, double s9, double rho0) {
+    const double Sxx = -(s1 * mneq[1] + 19.0 * s9 * mneq[9]) / (38.0 * rho0);
+    const double Syy = -(2.0 * s1 * mneq[1] - 19.0 * s9 * (mneq[9] - 3.0 * mneq[11])) / (76.0 * rho0);
+    const double Szz = -(2.0 * s1 * mneq[1] - 19.0 * s9 * (mneq[9] + 3.0 * mneq[11])) / (76.0 * rho0);
+    const double Sxy = -3.0 * s9 / (2.0 * rho0) * mneq[13];
+    const double Sxz = -3.0 * s9 / (2.0 * rho0) * mneq[15];
+    const double Syz = -3.0 * s9 / (2.0 * rho0) * mneq[14];
+    return sqrt(2.0 * (Sxx * Sxx + Syy * Syy + Szz * Szz +
+                       2.0 * Sxy * Sxy + 2.0 * Sxz * Sxz + 2.0 * Syz * Syz));
 }
 
 /* One cell's collision (eq. mrt_les_guo).  Outputs the post-collision
@@ -176,23 +192,19 @@ void orc_collide_cell(const orc_params* p, const double f[Q], const double F[3],
     double mneq[Q];
     for (int r = 0; r < Q; ++r) mneq[r] = m[r] - meq[r];
 
-    /* strain rate, eq. yu_strain (delta_t = 1), with s_1 = s_e, s_9 = 1/tau0 */
-    const double s1 = p->s_e, s9 = 1.0 / p->tau0;
-    const double Sxx = -(s1 * mneq[1] + 19.0 * s9 * mneq[9]) / (38.0 * rho0);
-    const double Syy = -(2.0 * s1 * mneq[1] - 19.0 * s9 * (mneq[9] - 3.0 * mneq[11])) / (76.0 * rho0);
-    const double Szz = -(2.0 * s1 * mneq[1] - 19.0 * s9 * (mneq[9] + 3.0 * mneq[11])) / (76.0 * rho0);
-    const double Sxy = -3.0 * s9 / (2.0 * rho0) * mneq[13];
-    const double Sxz = -3.0 * s9 / (2.0 * rho0) * mneq[15];
-    const double Syz = -3.0 * s9 / (2.0 * rho0) * mneq[14];
-    /* eq. strain_norm */
-    const double Snorm = sqrt(2.0 * (Sxx * Sxx + Syy * Syy + Szz * Szz +
-                                     2.0 * Sxy * Sxy + 2.0 * Sxz * Sxz + 2.0 * Syz * Syz));
-
     /* eq. bare_viscosity, eq. eddy_visc, eq. les_viscosity (Delta = 1) */
     const double nu0 = (p->tau0 - 0.5) / 3.0;
     const double Cm = (p->smag_form == 1) ? p->C * p->C : p->C;
-    const double nu_t = Cm * Snorm;
-    const double tau_e = 0.5 + 3.0 * (nu0 + nu_t);
+    double tau_e;
+    if (p->tau_mode == 1) {
+        /* S(s_1 = 0, s_9) = s_9 S(0, 1) and s_9 = 1/tau_e, so
+         * tau_e = tau0 + 3 Cm |S(0, 1)| / tau_e: the positive root of the quadratic */
+        const double S1 = strain_norm_of(mneq, 0.0, 1.0, rho0);
+        tau_e = 0.5 * (p->tau0 + sqrt(p->tau0 * p->tau0 + 12.0 * Cm * S1));
+    } else {
+        const double Snorm = strain_norm_of(mneq, p->s_e, 1.0 / p->tau0, rho0);
+        tau_e = 0.5 + 3.0 * (nu0 + Cm * Snorm);
+    }
     const double s_nu = 1.0 / tau_e;
 
     /* eq. relaxation-matrix */

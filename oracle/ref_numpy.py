@@ -15,7 +15,9 @@ Readings of the paper used here (each is also listed in the design notes):
   populations f - w rho0: its row 0 is delta-rho.  With full populations the
   rest-state moments M w rho0 = rho0 (1, -11, 3, 0, ..., 0) are added back.
 * eq. yu_strain uses s_1 = 1.19 and s_9 = 1/tau0 (the bare shear rate), so
-  tau_e follows from printed formulas without iteration.
+  tau_e follows from printed formulas without iteration (``tau_mode=0``).  The
+  alternative ``tau_mode=1`` makes it self-consistent: s_9 = 1/tau_e and the
+  divergence (m_1) term dropped, solved in closed form (``effective_tau_sc``).
 * nu_t = C Delta^2 |S| with the model constant C entering linearly
   (eq. eddy_visc); ``smag_form=1`` squares it (C_s^2 convention).
 * Delta = delta_x = delta_t = rho0 = 1 (App. A; App. B.1).
@@ -150,11 +152,25 @@ def effective_tau(tau0, C, Snorm, smag_form=0, Delta=1.0):
     return 0.5 + 3.0 * (nu0 + nu_t)
 
 
+def effective_tau_sc(tau0, C, mneq, smag_form=0, rho0=1.0, Delta=1.0):
+    """Self-consistent tau_e (reading of Sec. 2.3 / App. B.1 with s_9 = 1/tau_e).
+
+    With the m_1 term of eq. yu_strain dropped, S is linear in s_9:
+    S(s_9) = s_9 S_1, S_1 = eq. yu_strain at s_1 = 0, s_9 = 1.  Then
+    tau_e = tau0 + 3 C Delta^2 |S_1| / tau_e, a quadratic whose positive root is
+    tau_e = (tau0 + sqrt(tau0^2 + 12 C Delta^2 |S_1|)) / 2.
+    """
+    S1 = strain_norm(strain_tensor(mneq, s1=0.0, s9=1.0, rho0=rho0))
+    Cm = C if smag_form == 0 else C * C
+    return 0.5 * (tau0 + np.sqrt(tau0 * tau0 + 12.0 * Cm * Delta ** 2 * S1))
+
+
 def collide(f, F, tau0, C, smag_form=0, rho0=1.0,
-            s_e=L.S_E, s_eps=L.S_EPS, s_q=L.S_Q, s_pi=L.S_PI, s_m=L.S_M):
+            s_e=L.S_E, s_eps=L.S_EPS, s_q=L.S_Q, s_pi=L.S_PI, s_m=L.S_M, tau_mode=0):
     """Post-collision populations of eq. mrt_les_guo, per cell, in the paper's order.
 
-    f: (19, ...) full populations, F: (3, ...) body force.
+    f: (19, ...) full populations, F: (3, ...) body force.  tau_mode 0: s_9 = 1/tau0
+    in eq. yu_strain; 1: self-consistent s_9 = 1/tau_e (``effective_tau_sc``).
     Returns (f_star, info) with info = dict(rho, u, tau_e, Snorm).
     """
     rho, u = macroscopic(f, F)
@@ -162,9 +178,13 @@ def collide(f, F, tau0, C, smag_form=0, rho0=1.0,
     meq = equilibrium_moments(rho, u, rho0)
     Fm = force_moments(u, F)
     mneq = m - meq
-    S = strain_tensor(mneq, s1=s_e, s9=1.0 / tau0, rho0=rho0)
-    Snorm = strain_norm(S)
-    tau_e = effective_tau(tau0, C, Snorm, smag_form)
+    if tau_mode == 0:
+        S = strain_tensor(mneq, s1=s_e, s9=1.0 / tau0, rho0=rho0)
+        Snorm = strain_norm(S)
+        tau_e = effective_tau(tau0, C, Snorm, smag_form)
+    else:
+        tau_e = effective_tau_sc(tau0, C, mneq, smag_form, rho0)
+        Snorm = strain_norm(strain_tensor(mneq, s1=0.0, s9=1.0 / tau_e, rho0=rho0))
     Lam = L.relaxation_diagonal(1.0 / tau_e, s_e, s_eps, s_q, s_pi, s_m)
     mstar = m - Lam * mneq + (1.0 - 0.5 * Lam) * Fm
     fstar = np.tensordot(L.MINV, mstar, axes=([1], [0]))

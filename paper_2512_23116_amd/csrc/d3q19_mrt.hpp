@@ -45,10 +45,15 @@ template <typename R>
 struct CollideConst {
     R tau0;      // bare relaxation time
     R c3;        // 3 C (linear form) or 3 C^2; tau_e = tau0 + c3 |S|
-    R a_e;       // s_e / (38 rho0): coefficient of m1_neq in S_aa (eq. yu_strain)
-    R b9;        // s_9 / (2 rho0) with s_9 = 1/tau0: coefficient of m9_neq in S_xx
+    R a_e;       // s_e / (38 rho0): coefficient of m1_neq in S_aa (eq. yu_strain);
+                 // 0 in the self-consistent mode
+    R b9;        // s_9 / (2 rho0): coefficient of m9_neq in S_xx; s_9 = 1/tau0
+                 // (explicit mode) or 1 (self-consistent mode: |S| = |S_1| / tau_e)
     R s_e, s_eps, s_q, s_pi, s_m;
     R rho0;
+    R tau0_sq;   // tau0^2
+    int32_t self_consistent;   // 1: s_9 = 1/tau_e in eq. yu_strain, closed form
+    int32_t pad;
 };
 
 // Result of the macroscopic / closure half of the collision.
@@ -119,7 +124,8 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
     const R n14 = m14 - ruy * uz;
     const R n15 = m15 - rux * uz;
 
-    // eq. yu_strain with s_1 = s_e, s_9 = 1/tau0; eq. strain_norm
+    // eq. yu_strain with s_1 = s_e, s_9 = 1/tau0 (explicit mode) or without the
+    // s_1 term and s_9 = 1 (self-consistent mode, rescaled below); eq. strain_norm
     const R tr = k.a_e * n1;
     const R Sxx = -tr - k.b9 * n9;
     const R Syy = -tr + h * k.b9 * (n9 - R(3) * n11);
@@ -129,7 +135,17 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
     const R S2 = R(2) * (Sxx * Sxx + Syy * Syy + Szz * Szz) +
                  R(4) * (Sxy * Sxy + Sxz * Sxz + Syz * Syz);
     // eq. les_viscosity: tau_e = 1/2 + 3 (nu0 + C Delta^2 |S|) = tau0 + 3 C |S|
-    const R tau_t = k.c3 * fast_sqrt(S2);
+    R tau_t = k.c3 * fast_sqrt(S2);
+    if (k.self_consistent) {
+        // (the empty asm keeps this a uniform branch instead of computing it
+        // always and selecting, so the default mode pays nothing for it)
+        asm volatile("");
+        // |S| = X / tau_e with X = |S_1| (computed above with s_9 = 1, no m1
+        // term): tau_e^2 - tau0 tau_e - c3 X = 0.  Its positive root, as the
+        // increment over tau0 without cancellation:
+        // tau_e - tau0 = 2 c3 X / (tau0 + sqrt(tau0^2 + 4 c3 X)).
+        tau_t = R(2) * tau_t * fast_rcp(k.tau0 + fast_sqrt(k.tau0_sq + R(4) * tau_t));
+    }
     const R tau_e = k.tau0 + tau_t;
 
     CellMacro<R> out{m0, rho, ux, uy, uz, tau_t};

@@ -105,7 +105,7 @@ bool validate(const lbm_config* c, std::string* why) {
         (c->steps_per_graph < 2 || c->steps_per_graph > 1024 || (c->steps_per_graph & 1)))
         return bad("steps_per_graph must be 0 or even in [2, 1024]");
     if (c->temporal_block < 0 || c->temporal_block > 2) return bad("temporal_block must be 0, 1 or 2");
-    if (c->reserved != 0) return bad("reserved must be 0");
+    if (c->tau_mode != 0 && c->tau_mode != 1) return bad("tau_mode must be 0 or 1");
     if (c->temporal_block == 2) {
         if (c->streaming != LBM_STREAM_AB) return bad("temporal_block 2 needs A/B streaming");
         if (c->precision == LBM_FP64) return bad("temporal_block 2 needs 32- or 16-bit storage");
@@ -309,13 +309,19 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_handle** out) {
     a.rowc = h->rowc;
     a.xtab = h->xtab;
     // eq. les_viscosity: tau_e = tau0 + 3 C |S| (C^2 for smag_form 1), Delta = 1;
-    // eq. yu_strain with s_1 = s_e and s_9 = 1/tau0, delta_t = 1
+    // eq. yu_strain at delta_t = 1 (rates per tau_mode below)
     const double Cm = cfg->smag_form == 1 ? cfg->smag_C * cfg->smag_C : cfg->smag_C;
     CollideConst<double>& kd = a.kd;
     kd.tau0 = cfg->tau0;
     kd.c3 = 3.0 * Cm;
-    kd.a_e = cfg->s_e / (38.0 * cfg->rho0);
-    kd.b9 = (1.0 / cfg->tau0) / (2.0 * cfg->rho0);
+    // explicit: s_1 = s_e, s_9 = 1/tau0 in eq. yu_strain; self-consistent: no s_1
+    // term, strain evaluated at s_9 = 1 and rescaled by 1/tau_e in the closed form
+    const bool sc = cfg->tau_mode == 1;
+    kd.a_e = sc ? 0.0 : cfg->s_e / (38.0 * cfg->rho0);
+    kd.b9 = (sc ? 1.0 : 1.0 / cfg->tau0) / (2.0 * cfg->rho0);
+    kd.tau0_sq = cfg->tau0 * cfg->tau0;
+    kd.self_consistent = sc ? 1 : 0;
+    kd.pad = 0;
     kd.s_e = cfg->s_e; kd.s_eps = cfg->s_eps; kd.s_q = cfg->s_q; kd.s_pi = cfg->s_pi;
     kd.s_m = cfg->s_m;
     kd.rho0 = cfg->rho0;
@@ -323,6 +329,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_handle** out) {
     kf.tau0 = (float)kd.tau0; kf.c3 = (float)kd.c3; kf.a_e = (float)kd.a_e; kf.b9 = (float)kd.b9;
     kf.s_e = (float)kd.s_e; kf.s_eps = (float)kd.s_eps; kf.s_q = (float)kd.s_q;
     kf.s_pi = (float)kd.s_pi; kf.s_m = (float)kd.s_m; kf.rho0 = (float)kd.rho0;
+    kf.tau0_sq = (float)kd.tau0_sq; kf.self_consistent = kd.self_consistent; kf.pad = 0;
     a.tau0 = cfg->tau0;
     a.rho0 = cfg->rho0;
     a.sigma = h->cfg.storage_scale;

@@ -53,7 +53,7 @@ class lbm_config(ctypes.Structure):
         ("s_pi", ctypes.c_double), ("s_m", ctypes.c_double),
         ("storage_scale", ctypes.c_double),
         ("n_force_modes", ctypes.c_int32), ("steps_per_graph", ctypes.c_int32),
-        ("temporal_block", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("temporal_block", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
         ("force_modes", ctypes.POINTER(lbm_force_mode)),
         ("hip_stream", ctypes.c_void_p),
         ("device_buffer", ctypes.c_void_p),
@@ -298,7 +298,7 @@ class Lattice:
 
     def __init__(self, shape, tau0, C, modes=(), precision="fp32", streaming="aa",
                  smag_form=0, steps_per_graph=64, storage_scale=0.0, stream=None, rho0=1.0,
-                 temporal_block=0):
+                 temporal_block=0, tau_mode=0):
         import torch
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
@@ -314,6 +314,7 @@ class Lattice:
         cfg.storage_scale = storage_scale
         cfg.steps_per_graph = steps_per_graph
         cfg.temporal_block = temporal_block
+        cfg.tau_mode = tau_mode
         self._modes = make_modes(list(modes))
         cfg.n_force_modes = len(modes)
         cfg.force_modes = ctypes.cast(self._modes, ctypes.POINTER(lbm_force_mode))

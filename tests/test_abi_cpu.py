@@ -78,7 +78,7 @@ def test_config_defaults_and_required_bytes(lbm):
     ("nx", 0), ("tau0", 0.5), ("tau0", float("nan")), ("smag_C", -0.1), ("precision", 7),
     ("streaming", 2), ("smag_form", 2), ("rho0", 0.0), ("s_m", 2.0), ("storage_scale", 3.0),
     ("steps_per_graph", 3), ("steps_per_graph", 2048), ("n_force_modes", 65),
-    ("temporal_block", 3), ("temporal_block", 2), ("reserved", 1),
+    ("temporal_block", 3), ("temporal_block", 2), ("tau_mode", 2), ("tau_mode", -1),
 ])
 def test_invalid_configs_are_rejected_on_the_host(lbm, field, value):
     c = lbm.lbm_config_default()

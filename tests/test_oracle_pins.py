@@ -172,6 +172,47 @@ def test_strain_from_moments_recovers_chapman_enskog_strain(seed, orc):
     lat2 = orc.Lattice((1, 1, 1), tau0, C, smag_form=1)
     _, _, _, tau2 = lat2.collide_cell(f, np.zeros(3))
     assert abs(tau2 - (tau0 + 3 * C * C * Sn)) < 1e-14
+    # self-consistent mode: the deviatoric f^neq was made with tau0, so the
+    # estimate at s_9 = 1/tau_e is tau0 S_dev / tau_e and
+    # tau_e = tau0 + 3 C tau0 |S_dev| / tau_e
+    Sd = S - np.trace(S) / 3 * np.eye(3)
+    Sdn = math.sqrt(2 * (Sd * Sd).sum())
+    lat3 = orc.Lattice((1, 1, 1), tau0, C, tau_mode=1)
+    _, _, _, tau3 = lat3.collide_cell(f, np.zeros(3))
+    assert abs(tau3 - 0.5 * (tau0 + math.sqrt(tau0 ** 2 + 12 * C * tau0 * Sdn))) < 1e-14
+    assert abs(tau3 - (tau0 + 3 * C * tau0 * Sdn / tau3)) < 1e-14
+
+
+@pytest.mark.parametrize("smag_form", [0, 1])
+def test_self_consistent_tau_is_the_velocity_space_closed_form(smag_form, orc):
+    """tau_mode 1 equals the closed form built from the non-equilibrium stress in
+    velocity space: Pi = sum_a c_a c_a (f_a - f^eq_a) (eq. feq), its deviatoric part,
+    Q = sqrt(2 Pi_dev : Pi_dev), tau_e = (tau0 + sqrt(tau0^2 + 18 C Q / rho0)) / 2.
+    It also solves its defining relation tau_e = tau0 + 3 C |S(s_9 = 1/tau_e)|."""
+    rng = np.random.default_rng(40 + smag_form)
+    rho, u, F = _rand_state(rng, (13,))
+    f = R.feq(rho, u) + 2e-3 * rng.standard_normal((19, 13))
+    tau0, C = 0.507, 0.16
+    Cm = C if smag_form == 0 else C * C
+    fs, info = R.collide(f, F, tau0, C, smag_form=smag_form, tau_mode=1)
+    r, uu = R.macroscopic(f, F)
+    fneq = f - R.feq(r, uu)
+    Pi = np.einsum("ai,aj,ac->ijc", CF, CF, fneq)
+    Pd = Pi - np.einsum("iic->c", Pi) / 3 * np.eye(3)[:, :, None]
+    Qn = np.sqrt(2 * (Pd * Pd).sum((0, 1)))
+    hou = 0.5 * (tau0 + np.sqrt(tau0 ** 2 + 18 * Cm * Qn))
+    np.testing.assert_allclose(info["tau_e"], hou, rtol=1e-14)
+    np.testing.assert_allclose(info["tau_e"],
+                               R.effective_tau(tau0, C, info["Snorm"], smag_form), rtol=1e-14)
+    assert np.all(info["tau_e"] >= tau0)
+    # the explicit mode differs, by the factor tau0 / tau_e on nu_t and the m_1 term
+    _, info0 = R.collide(f, F, tau0, C, smag_form=smag_form, tau_mode=0)
+    assert np.abs(info0["tau_e"] - info["tau_e"]).max() > 1e-9
+    lat = orc.Lattice((1, 1, 1), tau0, C, smag_form=smag_form, tau_mode=1)
+    for c in range(13):
+        out, _, _, tau = lat.collide_cell(f[:, c], F[:, c])
+        np.testing.assert_allclose(out, fs[:, c], rtol=0, atol=1e-15)
+        assert abs(tau - info["tau_e"][c]) < 1e-15
 
 
 def test_les_reduces_to_dns_when_C_is_zero(orc):
@@ -214,26 +255,28 @@ def test_uniform_flow_stays_uniform(orc):
 
 # ------------------------------------------------ C oracle == numpy definition ---
 
-@pytest.mark.parametrize("shape,tau0,C,smag,nsteps", [
-    ((8, 8, 8), 0.52, 0.13, 0, 3),
-    ((5, 7, 6), 0.505, 0.18, 0, 4),
-    ((4, 3, 9), 0.7, 0.1, 1, 2),
-    ((2, 2, 2), 0.51, 0.1, 0, 3),
-    ((1, 1, 1), 0.51, 0.1, 0, 2),
-    ((1, 6, 1), 0.6, 0.0, 0, 5),
+@pytest.mark.parametrize("shape,tau0,C,smag,nsteps,tm", [
+    ((8, 8, 8), 0.52, 0.13, 0, 3, 0),
+    ((5, 7, 6), 0.505, 0.18, 0, 4, 0),
+    ((4, 3, 9), 0.7, 0.1, 1, 2, 0),
+    ((2, 2, 2), 0.51, 0.1, 0, 3, 0),
+    ((1, 1, 1), 0.51, 0.1, 0, 2, 0),
+    ((1, 6, 1), 0.6, 0.0, 0, 5, 0),
+    ((8, 8, 8), 0.52, 0.13, 0, 3, 1),
+    ((4, 3, 9), 0.505, 0.18, 1, 2, 1),
 ])
-def test_c_oracle_matches_dense_definition(shape, tau0, C, smag, nsteps, orc):
+def test_c_oracle_matches_dense_definition(shape, tau0, C, smag, nsteps, tm, orc):
     modes = [((0, 1, 0), (1e-4, 0, 0), 0.0), ((1, -2, 1), (2e-5, -1e-5, 3e-5), 0.7),
              ((2, 0, 1), (1e-5, 2e-5, -1e-5), 1.3)]
     f0 = I.initial_populations(I.KIND_NOISE, shape, 0.05, 11)
-    lat = orc.Lattice(shape, tau0, C, modes, smag_form=smag)
+    lat = orc.Lattice(shape, tau0, C, modes, smag_form=smag, tau_mode=tm)
     np.testing.assert_array_equal(lat.init(I.KIND_NOISE, 0.05, 11), f0)
     a = lat.step(f0, nsteps)
-    b = R.step(f0, tau0, C, modes, smag_form=smag, nsteps=nsteps)
+    b = R.step(f0, tau0, C, modes, smag_form=smag, nsteps=nsteps, tau_mode=tm)
     scale = np.abs(b - L.W.reshape(19, 1, 1, 1)).max()
     assert np.abs(a - b).max() <= 1e-13 * scale
     rho, u, tau = lat.fields(a)
-    d = R.diagnostics(a, tau0, C, modes, smag_form=smag)
+    d = R.diagnostics(a, tau0, C, modes, smag_form=smag, tau_mode=tm)
     np.testing.assert_allclose(tau - 0.5, d["theta"], rtol=1e-13, atol=1e-16)
     np.testing.assert_allclose(u, d["u"], rtol=0, atol=1e-16)
     np.testing.assert_allclose(rho, d["rho"], rtol=1e-15)
