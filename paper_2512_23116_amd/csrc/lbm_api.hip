@@ -158,10 +158,9 @@ lbm_status capture_graph(lbm_handle* h) {
         LatticeArgs a = h->args;
         int pat = PAT_AB;
         if (h->cfg.streaming == LBM_STREAM_AB) {
-            a.a = h->state[k & 1];
-            a.b = h->state[(k & 1) ^ 1];
+            set_arrays(a, h->state[k & 1], h->state[(k & 1) ^ 1]);
         } else {
-            a.a = a.b = h->state[0];
+            set_arrays(a, h->state[0], h->state[0]);
             pat = (k & 1) ? PAT_AA_ODD : PAT_AA_EVEN;
         }
         hipError_t e = tb2 ? launch_step_tb2(h->cfg.precision, a, h->cap_stream)
@@ -195,13 +194,22 @@ int current_pattern(const lbm_handle* h) {
     return (h->steps & 1) ? PAT_AA_ODD : PAT_AA_EVEN;
 }
 
+void set_arrays(LatticeArgs& L, void* a, void* b) {
+    L.a = a;
+    L.b = b;
+    const uint64_t pbytes = L.plane * (uint64_t)L.elem_bytes;
+    for (int i = 0; i < 19; ++i) {
+        L.pa[i] = (char*)a + (uint64_t)i * pbytes;
+        L.pb[i] = (char*)b + (uint64_t)i * pbytes;
+    }
+}
+
 LatticeArgs current_args(const lbm_handle* h) {
     LatticeArgs a = h->args;
     if (h->cfg.streaming == LBM_STREAM_AB) {
-        a.a = h->state[h->cur];
-        a.b = h->state[h->cur ^ 1];
+        set_arrays(a, h->state[h->cur], h->state[h->cur ^ 1]);
     } else {
-        a.a = a.b = h->state[0];
+        set_arrays(a, h->state[0], h->state[0]);
     }
     return a;
 }
@@ -301,6 +309,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_handle** out) {
 
     LatticeArgs& a = h->args;
     a.plane = h->plane_elems;
+    a.elem_bytes = (uint32_t)h->elem_bytes;
     a.nx = cfg->nx; a.ny = cfg->ny; a.nz = cfg->nz;
     a.nxy = (uint32_t)cfg->nx * cfg->ny;
     a.ncell = (uint32_t)nc;

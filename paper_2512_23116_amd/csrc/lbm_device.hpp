@@ -117,27 +117,43 @@ __device__ __forceinline__ uint32_t block_id(const LatticeArgs& L) {
     return b;
 }
 
-// Address of element c of plane `slot`: the 64-bit plane base is uniform
-// (SGPRs) and the per-lane part is a 32-bit byte offset (plane bytes < 2^32 is
-// enforced at create), which maps to global loads with a scalar base.
-template <typename T>
-__device__ __forceinline__ T* elem_ptr(T* base, int slot, uint64_t plane, uint32_t c) {
-    using B = std::conditional_t<std::is_const_v<T>, const char, char>;
-    B* pb = (B*)(base + (uint64_t)slot * plane);
-    return (T*)(pb + (uint32_t)(c * (uint32_t)sizeof(T)));
+// Plane addressing.  The 64-bit base of plane `slot` is uniform (SGPRs) and
+// the per-lane part is a 32-bit byte offset (plane bytes < 2^32 is enforced at
+// create), which maps to global loads and stores with a scalar base.  Two ways
+// to get the plane base:
+//  * PlaneTable: the 19 bases precomputed on the host, read from the kernel
+//    arguments (no scalar arithmetic; used where they need not stay live across
+//    a loop);
+//  * PlaneStride: array base + slot * plane bytes (a few scalar instructions,
+//    no extra SGPRs held; used by the z-marching two-step kernel).
+struct PlaneTable {
+    char* const* p;
+    __device__ __forceinline__ char* operator()(int slot) const { return p[slot]; }
+};
+struct PlaneStride {
+    char* base;
+    uint64_t bytes;
+    __device__ __forceinline__ char* operator()(int slot) const {
+        return base + (uint64_t)slot * bytes;
+    }
+};
+
+template <typename T, class Planes>
+__device__ __forceinline__ T* elem_ptr(const Planes& planes, int slot, uint32_t c) {
+    return (T*)(planes(slot) + (uint32_t)(c * (uint32_t)sizeof(T)));
 }
 
 // Location of the pre-collision f_i(x) for pattern PAT: slot and cell.
 //   AA_EVEN: (i, x)   AA_ODD: (opp i, x - c_i)   AB: (i, x - c_i)
-template <class Cd, int PAT, bool kNT = false>
-__device__ __forceinline__ void load_cell(const typename Cd::T* base, uint64_t plane, uint32_t cell,
+template <class Cd, int PAT, bool kNT = false, class Planes>
+__device__ __forceinline__ void load_cell(const Planes& planes, uint32_t cell,
                                           const Nbr& nb, typename Cd::R (&g)[19],
                                           typename Cd::R inv_s) {
     static_for<19>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int slot = (PAT == PAT_AA_ODD) ? opp_of(i) : i;
         const uint32_t c = (PAT == PAT_AA_EVEN) ? cell : cell + (uint32_t)off_minus<i>(nb);
-        const typename Cd::T* p = elem_ptr(base, slot, plane, c);
+        const typename Cd::T* p = elem_ptr<const typename Cd::T>(planes, slot, c);
         if constexpr (kNT) g[i] = dec<Cd>(__builtin_nontemporal_load(p), inv_s);
         else g[i] = dec<Cd>(*p, inv_s);
     });
@@ -145,15 +161,15 @@ __device__ __forceinline__ void load_cell(const typename Cd::T* base, uint64_t p
 
 // Where the post-collision f*_i(x) goes for pattern PAT (the pattern the step
 // reads with): AA_EVEN -> (opp i, x); AA_ODD -> (i, x + c_i); AB -> (i, x) of dst.
-template <class Cd, int PAT, bool kNT = false>
-__device__ __forceinline__ void store_cell(typename Cd::T* base, uint64_t plane, uint32_t cell,
+template <class Cd, int PAT, bool kNT = false, class Planes>
+__device__ __forceinline__ void store_cell(const Planes& planes, uint32_t cell,
                                            const Nbr& nb, const typename Cd::R (&g)[19],
                                            typename Cd::R s) {
     static_for<19>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int slot = (PAT == PAT_AA_EVEN) ? opp_of(i) : i;
         const uint32_t c = (PAT == PAT_AA_ODD) ? cell + (uint32_t)off_minus<opp_of(i)>(nb) : cell;
-        typename Cd::T* p = elem_ptr(base, slot, plane, c);
+        typename Cd::T* p = elem_ptr<typename Cd::T>(planes, slot, c);
         if constexpr (kNT) __builtin_nontemporal_store(enc<Cd>(g[i], s), p);
         else *p = enc<Cd>(g[i], s);
     });
@@ -202,7 +218,7 @@ __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT, (NT & 1) != 0>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
+    load_cell<Cd, PAT, (NT & 1) != 0>(PlaneTable{L.pa}, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     collide<R, true>(g, Fx, Fy, Fz, collide_const<R>(L));
@@ -212,7 +228,7 @@ __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
     // scalar-base + 32-bit-offset form as the loads.
     uint32_t cs = cell;
     asm volatile("" : "+v"(cs));
-    store_cell<Cd, PAT, (NT & 2) != 0>((T*)(PAT == PAT_AB ? L.b : L.a), L.plane, cs, nb, g,
+    store_cell<Cd, PAT, (NT & 2) != 0>(PlaneTable{PAT == PAT_AB ? L.pb : L.pa}, cs, nb, g,
                                        scale_of<R>(L));
 }
 

@@ -31,6 +31,9 @@ struct LatticeArgs {
     void* a;                 // population array (AA: the only one; AB: current source)
     void* b;                 // AB: destination; AA: == a
     uint64_t plane;          // elements per direction plane (padded); plane bytes < 2^32
+    char* pa[19];            // plane i of a: a + i * plane * element bytes
+    char* pb[19];            // plane i of b (precomputed on the host: kernels take the
+                             // 64-bit plane bases from kernel arguments, no scalar math)
     uint32_t nx, ny, nz, nxy, ncell;
     DivMagic mx, my;         // division by nx (cell -> row) and ny (row -> z)
     const void* rowc;        // force row coefficients [ny*nz][16] in R, or null
@@ -42,6 +45,8 @@ struct LatticeArgs {
     float sigma_f, inv_sigma_f;
     int32_t xcd_remap;       // remap block ids so each XCD walks a contiguous range
     int32_t nt_mode;         // step kernel: bit 1 non-temporal stores
+    uint32_t elem_bytes;     // bytes per stored population
+    uint32_t pad_;
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.
@@ -102,6 +107,8 @@ namespace lbm {
 // Current pattern and arrays of a handle for its step count / AB parity.
 int current_pattern(const lbm_handle* h);
 LatticeArgs current_args(const lbm_handle* h);
+// Point a (source) and b (destination) of L at two population arrays, with their planes.
+void set_arrays(LatticeArgs& L, void* a, void* b);
 // Advance h's bookkeeping after one launched step.
 void advance(lbm_handle* h);
 }  // namespace lbm

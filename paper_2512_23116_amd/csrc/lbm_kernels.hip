@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
         const CellPos p = decode(cell, L);
         const Nbr nb = make_nbr(p, L);
         R g[19];
-        load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
+        load_cell<Cd, PAT>(PlaneTable{L.pa}, cell, nb, g, inv_scale_of<R>(L));
         bool finite = true;
 #pragma unroll
         for (int i = 0; i < 19; ++i) finite = finite && isfinite(g[i]);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_moments(LatticeArgs L, double* rho, dou
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
+    load_cell<Cd, PAT>(PlaneTable{L.pa}, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     const CellMacro<R> m = collide<R, false>(g, Fx, Fy, Fz, collide_const<R>(L));
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
-    load_cell<Cd, PAT>((const T*)L.a, L.plane, cell, nb, g, inv_scale_of<R>(L));
+    load_cell<Cd, PAT>(PlaneTable{L.pa}, cell, nb, g, inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     const CellMacro<R> m = collide<R, false>(g, Fx, Fy, Fz, collide_const<R>(L));

@@ -86,9 +86,9 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     const uint32_t x2 = X0 + (uint32_t)ex - 1u, y2 = Y0 + (uint32_t)ey - 1u;
     const bool inner = ex >= 1 && ex <= TB_TX && ey >= 1 && ey <= TB_TY && x2 < L.nx && y2 < L.ny;
 
-    const T* src = (const T*)L.a;
-    T* dst = (T*)L.b;
     const R inv_s = inv_scale_of<R>(L), s_st = scale_of<R>(L);
+    const uint64_t pbytes = L.plane * (uint64_t)sizeof(T);
+    const PlaneStride src{(char*)L.a, pbytes}, dst{(char*)L.b, pbytes};
     const CollideConst<R>& k = collide_const<R>(L);
 
     auto plane1 = [&](int j) {   // z of the phase-1 plane of iteration j: Z0 - 1 + j, wrapped
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
         p.z = plane1(j);
         p.row = y1 + L.ny * p.z;
         const Nbr nb = make_nbr(p, L);
-        load_cell<Cd, PAT_AB>(src, L.plane, x1 + L.nx * p.row, nb, g, inv_s);
+        load_cell<Cd, PAT_AB>(src, x1 + L.nx * p.row, nb, g, inv_s);
     };
 
     // One iteration j: phase 1 on the prefetched pulls P of plane Z0 - 1 + j,
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
             const uint32_t cell = x2 + L.nx * p.row;
             static_for<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                *elem_ptr(dst, i, L.plane, cell) = enc<Cd>(g[i], s_st);
+                *elem_ptr<T>(dst, i, cell) = enc<Cd>(g[i], s_st);
             });
         }
         __syncthreads();
