@@ -34,19 +34,33 @@ struct BatchTable {
     SlotDesc slot[1];    // n_slots entries follow
 };
 
-__global__ __launch_bounds__(256) void k_batch_step(const BatchTable* tab, int k) {
+// The table is read through the constant address space (4) in device code: the
+// kernel never writes it, and uniform reads from that space become scalar loads
+// even after the kernel's own global stores (which would otherwise force vector
+// loads of the 38 plane pointers and the slot constants per tile).  The host
+// pass only checks the kernel body, which has no address spaces.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_CONSTANT_SPACE __attribute__((address_space(4)))
+#else
+#define LBM_CONSTANT_SPACE
+#endif
+typedef const LBM_CONSTANT_SPACE BatchTable ConstTable;
+
+__global__ __launch_bounds__(256) void k_batch_step(const BatchTable* tab_generic, int k) {
+    ConstTable* tab = (ConstTable*)tab_generic;
     const uint32_t ns = tab->n_slots, total = tab->total_tiles;
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         uint32_t s = 0;
         while (s + 1 < ns && tab->slot[s + 1].tile_begin <= t) ++s;
-        const SlotDesc& S = tab->slot[s];
-        if ((uint32_t)k >= S.nsteps) continue;
-        const uint32_t cell = (t - S.tile_begin) * 256u + threadIdx.x;
-        if (cell >= S.L.ncell) continue;
-        if (((S.parity0 + (uint32_t)k) & 1u) == 0u)
-            step_cell<CdF32, PAT_AA_EVEN>(S.L, cell);
+        if ((uint32_t)k >= tab->slot[s].nsteps) continue;
+        const uint32_t cell = (t - tab->slot[s].tile_begin) * 256u + threadIdx.x;
+        LatticeArgs L;
+        __builtin_memcpy(&L, (const LBM_CONSTANT_SPACE char*)&tab->slot[s].L, sizeof L);
+        if (cell >= L.ncell) continue;
+        if (((tab->slot[s].parity0 + (uint32_t)k) & 1u) == 0u)
+            step_cell<CdF32, PAT_AA_EVEN>(L, cell);
         else
-            step_cell<CdF32, PAT_AA_ODD>(S.L, cell);
+            step_cell<CdF32, PAT_AA_ODD>(L, cell);
     }
 }
 
