@@ -147,6 +147,13 @@ typedef struct {
     double energy;            /* (1/2) <u.u>, unweighted domain mean          */
     double energy_rho;        /* (1/2) <rho u.u>                              */
     int64_t n_nonfinite;      /* cells whose populations or tau_e are NaN/Inf */
+    double strain2;           /* <|S|^2> = 2 <S:S>, S the strain that sets tau_e
+                                 (eq. yu_strain); nu0 <|S|^2> is the resolved
+                                 dissipation 2 nu0 <S:S> of eq. energy_balance */
+    double nut_strain2;       /* <nu_t |S|^2>, nu_t = (tau_e - tau0) / 3: the
+                                 dissipation by the Smagorinsky viscosity     */
+    double injection;         /* <F.u>: power injected by the forcing
+                                 (eq. energy_balance)                          */
 } lbm_stats;
 
 /* Fill *cfg with the paper's defaults: 32^3, FP32, AA, tau0 = 0.51, C = 0.1,
@@ -219,6 +226,32 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
  * F4(r) = out[6j+3] / out[6j]^2.  FP64, reduced in a fixed order (bitwise
  * reproducible).  nr in 1..65535.  Allocates device temporaries.  Synchronises. */
 lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr, double* out);
+
+/* Turbulence scales of the current state (Sec. 2.2, eq. integral_length_scale,
+ * eq. kolmogorov_scale, eq. taylor_microscale, eq. rms_velocity,
+ * eq. dissipation_rate, eq. energy_balance) on a cubic N^3 lattice.  Spectral
+ * quantities use the shell spectrum of lbm_spectrum for shells 1..kmax
+ * (kmax <= 0: every shell) with wavenumber kappa = 2 pi k / N (lattice units,
+ * delta_x = 1; the paper's 2 pi box maps onto N cells) and the molecular
+ * viscosity nu0 = (tau0 - 1/2)/3.  Real-space quantities come from the FP64
+ * reductions of lbm_kt_stats.  INVALID_ARG for a non-cubic lattice.  Allocates
+ * device temporaries.  Synchronises. */
+typedef struct {
+    int32_t kmax;             /* shells summed: 1..kmax                      */
+    int32_t pad;
+    double energy;            /* 1/2 <u.u> in real space (eq. energy_balance) */
+    double energy_spec;       /* sum_{k=1..kmax} E(k) (the mean flow excluded) */
+    double u_rms;             /* sqrt(2 energy_spec / 3)                      */
+    double integral_scale;    /* L = (3 pi / 4) sum(E/kappa) / sum(E)         */
+    double eps_spec;          /* 2 nu0 sum kappa^2 E(k)                       */
+    double eps_strain;        /* 2 nu0 <S:S> = nu0 <|S|^2>, S of eq. yu_strain */
+    double eps_sgs;           /* <nu_t |S|^2>: Smagorinsky dissipation         */
+    double injection;         /* <F.u>                                       */
+    double eta;               /* (nu0^3 / eps_spec)^(1/4)                     */
+    double taylor;            /* sqrt(15 nu0 u_rms^2 / eps_spec)              */
+    double re_lambda;         /* u_rms taylor / nu0                           */
+} lbm_turbulence_stats;
+lbm_status lbm_turbulence(lbm_handle* h, int32_t kmax, lbm_turbulence_stats* out);
 
 /* Checkpoint / resume in the storage format: lbm_state_bytes() bytes of
  * opaque state (host memory) plus the step count.  Restoring into a handle

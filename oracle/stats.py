@@ -73,3 +73,45 @@ def structure_functions(u, rs):
                     (d2 * d2 * np.abs(du)).mean(), (d2 * d2 * d2).mean()]
         out[j] = acc / 3.0
     return out
+
+
+def turbulence_scales(u, nu0, snorm=None, tau_t=None, F=None):
+    """Turbulence scales of Sec. 2.2 for a velocity field u (3, N, N, N).
+
+    Reading: the shell index k of the N-cell periodic box is the wavenumber
+    kappa = 2 pi k / N in lattice units (the paper's 2 pi box maps onto N cells),
+    the mean flow (k = 0) is excluded, and the viscosity is the molecular
+    nu0 = (tau0 - 1/2)/3:
+      L = (3 pi / 4) sum(E / kappa) / sum(E)       eq. integral_length_scale
+      u_rms = sqrt(2 sum(E) / 3)                   eq. rms_velocity
+      eps_spec = 2 nu0 sum(kappa^2 E)              eq. dissipation_rate
+      eta = (nu0^3 / eps)^(1/4), lambda = sqrt(15 nu0 u_rms^2 / eps)
+                                                   eq. kolmogorov_scale, eq. taylor_microscale
+    Given the per-cell strain magnitude |S| (eq. strain_norm), tau_t = tau_e - tau0
+    and the force F: eps_strain = 2 nu0 <S:S> = nu0 <|S|^2>, eps_sgs = <nu_t |S|^2>
+    with nu_t = tau_t / 3, injection = <F.u> (eq. energy_balance).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[1]
+    assert u.shape[1:] == (N, N, N), "a cubic lattice"
+    E = energy_spectrum(u)
+    k = np.arange(1, E.size)
+    kap = 2.0 * np.pi * k / N
+    Ek = E[1:]
+    e = Ek.sum()
+    out = dict(energy=0.5 * (u * u).sum(0).mean(), energy_spec=e,
+               u_rms=np.sqrt(2.0 * e / 3.0),
+               integral_scale=0.75 * np.pi * (Ek / kap).sum() / e,
+               eps_spec=2.0 * nu0 * (kap * kap * Ek).sum())
+    eps = out["eps_spec"]
+    out["eta"] = (nu0 ** 3 / eps) ** 0.25
+    out["taylor"] = np.sqrt(15.0 * nu0 * out["u_rms"] ** 2 / eps)
+    out["re_lambda"] = out["u_rms"] * out["taylor"] / nu0
+    if snorm is not None:
+        s2 = np.asarray(snorm, dtype=np.float64) ** 2
+        out["eps_strain"] = nu0 * s2.mean()
+        if tau_t is not None:
+            out["eps_sgs"] = (np.asarray(tau_t) / 3.0 * s2).mean()
+    if F is not None:
+        out["injection"] = (np.asarray(F) * u).sum(0).mean()
+    return out

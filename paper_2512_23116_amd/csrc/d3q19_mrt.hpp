@@ -62,6 +62,7 @@ struct CellMacro {
     R drho;    // rho - rho0 (exact moment sum, kept for FP64 mass reductions)
     R rho, ux, uy, uz;
     R tau_t;   // tau_e - tau0 = 3 C Delta^2 |S| (or 3 C^2 Delta^2 |S|)
+    R snorm2;  // |S|^2 = 2 S:S of the strain that sets tau_e (diagnostics only)
 };
 
 // Collide one cell in place.  g: deviation populations (pre-collision in,
@@ -147,8 +148,11 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
         tau_t = R(2) * tau_t * fast_rcp(k.tau0 + fast_sqrt(k.tau0_sq + R(4) * tau_t));
     }
     const R tau_e = k.tau0 + tau_t;
+    // |S|^2: S2 itself, or (|S_1| / tau_e)^2 in the self-consistent mode.  Only the
+    // diagnostics read it; the step kernels drop it.
+    const R snorm2 = k.self_consistent ? S2 * fast_rcp(tau_e * tau_e) : S2;
 
-    CellMacro<R> out{m0, rho, ux, uy, uz, tau_t};
+    CellMacro<R> out{m0, rho, ux, uy, uz, tau_t, snorm2};
     if constexpr (!kFull) {
         return out;
     } else {

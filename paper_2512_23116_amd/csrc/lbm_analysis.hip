@@ -1,11 +1,17 @@
 // lbm_analysis.hip — on-device turbulence diagnostics of the current state:
 // the shell-binned kinetic-energy spectrum (Sec. 2.2, eq. integral_length_scale
-// with the squared modulus) and longitudinal structure functions / flatness
-// (Sec. 5.3).  Both start from the velocity with the half-force shift
-// (eq. guo_velocity) that lbm_moments returns, computed on the device in FP64.
+// with the squared modulus), longitudinal structure functions / flatness
+// (Sec. 5.3), and the turbulence scales of Sec. 2.2 (integral scale,
+// dissipation, Kolmogorov and Taylor scales, energy balance terms).  All start
+// from the velocity with the half-force shift (eq. guo_velocity) that
+// lbm_moments returns, computed on the device in FP64.
 #include <hipfft/hipfft.h>
+#include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
 
 #include "lbm_device.hpp"
 
@@ -217,6 +223,48 @@ lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr,
                                             hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "structure functions");
+    return LBM_OK;
+}
+
+lbm_status lbm_turbulence(lbm_handle* h, int32_t kmax, lbm_turbulence_stats* out) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (!out) return set_err(h, LBM_ERR_INVALID_ARG, "out is NULL");
+    const uint32_t N = h->args.nx;
+    if (h->args.ny != N || h->args.nz != N)
+        return set_err(h, LBM_ERR_INVALID_ARG, "turbulence scales need a cubic lattice");
+    const int32_t kall = (int32_t)(0.5 * sqrt(3.0) * N + 1.0);   // every shell present
+    if (kmax <= 0 || kmax > kall) kmax = kall;
+    if (kmax > 4096) return set_err(h, LBM_ERR_INVALID_ARG, "lattice too large for the spectrum");
+    std::vector<double> E((size_t)kmax + 1);
+    lbm_status st = lbm_spectrum(h, kmax, E.data());
+    if (st != LBM_OK) return st;
+    lbm_stats s;
+    st = lbm_kt_stats(h, &s);
+    if (st != LBM_OK) return st;
+    // Sec. 2.2 with the shell index k of the N-cell box as the wavenumber
+    // kappa = 2 pi k / N in lattice units; the mean flow (k = 0) is excluded.
+    const double nu0 = (h->cfg.tau0 - 0.5) / 3.0;
+    double e = 0.0, e_over_k = 0.0, k2e = 0.0;
+    for (int32_t k = 1; k <= kmax; ++k) {
+        const double kap = 2.0 * M_PI * k / N;
+        e += E[k];
+        e_over_k += E[k] / kap;
+        k2e += kap * kap * E[k];
+    }
+    memset(out, 0, sizeof *out);
+    out->kmax = kmax;
+    out->energy = s.energy;
+    out->energy_spec = e;
+    out->u_rms = sqrt(2.0 * e / 3.0);                        // eq. rms_velocity
+    out->integral_scale = e > 0.0 ? 0.75 * M_PI * e_over_k / e : NAN;   // eq. integral_length_scale
+    out->eps_spec = 2.0 * nu0 * k2e;                          // eq. dissipation_rate
+    out->eps_strain = nu0 * s.strain2;                        // 2 nu0 <S:S>
+    out->eps_sgs = s.nut_strain2;
+    out->injection = s.injection;                             // <F.u>
+    const double eps = out->eps_spec;
+    out->eta = eps > 0.0 ? pow(nu0 * nu0 * nu0 / eps, 0.25) : NAN;          // eq. kolmogorov_scale
+    out->taylor = eps > 0.0 ? sqrt(15.0 * nu0 * out->u_rms * out->u_rms / eps) : NAN;  // eq. taylor_microscale
+    out->re_lambda = out->u_rms * out->taylor / nu0;
     return LBM_OK;
 }
 

@@ -434,7 +434,7 @@ lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out) {
                                result, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "diagnostic kernel");
     double r[kDiagSlots];
-    HIPCHK(h, hipMemcpyAsync(r, result, 13 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(r, result, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     lbm_status st = sync(h);
     if (st != LBM_OK) return st;
 
@@ -471,6 +471,9 @@ lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out) {
     out->momentum[2] = r[9];
     out->energy = r[10] / n;
     out->energy_rho = r[11] / n;
+    out->strain2 = r[13] / n;
+    out->nut_strain2 = r[14] / (3.0 * n);   // nu_t = tau_t / 3
+    out->injection = r[15] / n;
     if (out->n_nonfinite > 0)
         return fail(h, LBM_ERR_UNSTABLE, "%lld non-finite cells", (long long)out->n_nonfinite);
     return LBM_OK;

@@ -29,7 +29,10 @@ __global__ __launch_bounds__(256) void k_step(LatticeArgs L) {
 // ----------------------------------------------------- diagnostics ---
 // Per-block FP64 partials: [0..3] sum of tau_t^p (p = 1..4, tau_t = tau_e - tau0),
 // [4] min tau_t, [5] max tau_t, [6] sum delta rho, [7..9] sum rho u,
-// [10] sum u.u/2, [11] sum rho u.u/2, [12] non-finite cells.
+// [10] sum u.u/2, [11] sum rho u.u/2, [12] non-finite cells, [13] sum |S|^2,
+// [14] sum tau_t |S|^2 (3 nu_t |S|^2), [15] sum F.u (power injected, eq. energy_balance).
+constexpr int kDiagUsed = 16;
+static_assert(kDiagUsed <= kDiagSlots, "diagnostic partials overflow their slots");
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -48,9 +51,9 @@ template <class Cd, int PAT>
 __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
     using T = typename Cd::T;
     using R = typename Cd::R;
-    double acc[13];
+    double acc[kDiagUsed];
 #pragma unroll
-    for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kDiagUsed; ++j) acc[j] = 0.0;
     acc[4] = INFINITY;
     acc[5] = -INFINITY;
     const CollideConst<R>& k = collide_const<R>(L);
@@ -82,17 +85,20 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
         acc[7] += rho * ux; acc[8] += rho * uy; acc[9] += rho * uz;
         const double uu = 0.5 * (ux * ux + uy * uy + uz * uz);
         acc[10] += uu; acc[11] += rho * uu;
+        const double s2 = (double)m.snorm2;
+        acc[13] += s2; acc[14] += tt * s2;
+        acc[15] += (double)Fx * ux + (double)Fy * uy + (double)Fz * uz;
     }
     __shared__ double red[4][16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < 13; ++j) {
+    for (int j = 0; j < kDiagUsed; ++j) {
         double v = acc[j];
         v = (j == 4) ? wave_min(v) : ((j == 5) ? wave_max(v) : wave_sum(v));
         if (lane == 0) red[wv][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 13) {
+    if (threadIdx.x < kDiagUsed) {
         const int j = threadIdx.x;
         double v = red[0][j];
         for (int w = 1; w < 4; ++w)
@@ -101,11 +107,11 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
     }
 }
 
-// Reduce the per-block partials in a fixed order into result[0..12].
+// Reduce the per-block partials in a fixed order into result[0..15].
 __global__ __launch_bounds__(256) void k_diag_final(const double* partials, int nblocks,
                                                     double* result) {
     __shared__ double red[256];
-    for (int j = 0; j < 13; ++j) {
+    for (int j = 0; j < kDiagUsed; ++j) {
         double v = (j == 4) ? INFINITY : ((j == 5) ? -INFINITY : 0.0);
         for (int b = threadIdx.x; b < nblocks; b += 256) {
             const double x = partials[(uint64_t)b * kDiagSlots + j];

@@ -34,7 +34,7 @@ EXPORTS = (
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
-    "lbm_spectrum", "lbm_structure_functions",
+    "lbm_spectrum", "lbm_structure_functions", "lbm_turbulence",
 )
 
 
@@ -73,6 +73,8 @@ class lbm_stats(ctypes.Structure):
         ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
         ("energy", ctypes.c_double), ("energy_rho", ctypes.c_double),
         ("n_nonfinite", ctypes.c_int64),
+        ("strain2", ctypes.c_double), ("nut_strain2", ctypes.c_double),
+        ("injection", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -81,6 +83,20 @@ class lbm_stats(ctypes.Structure):
             v = getattr(self, name)
             out[name] = list(v) if name == "momentum" else v
         return out
+
+
+class lbm_turbulence_stats(ctypes.Structure):
+    _fields_ = [
+        ("kmax", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("energy", ctypes.c_double), ("energy_spec", ctypes.c_double),
+        ("u_rms", ctypes.c_double), ("integral_scale", ctypes.c_double),
+        ("eps_spec", ctypes.c_double), ("eps_strain", ctypes.c_double),
+        ("eps_sgs", ctypes.c_double), ("injection", ctypes.c_double),
+        ("eta", ctypes.c_double), ("taylor", ctypes.c_double), ("re_lambda", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
 
 class LbmError(RuntimeError):
@@ -119,6 +135,8 @@ def lib():
         "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
         "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
                                                    ctypes.c_int32, dp]),
+        "lbm_turbulence": (ctypes.c_int, [H, ctypes.c_int32,
+                                          ctypes.POINTER(lbm_turbulence_stats)]),
         "lbm_state_bytes": (ctypes.c_size_t, [H]),
         "lbm_save_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -251,6 +269,12 @@ def lbm_structure_functions(h, rs):
     return out
 
 
+def lbm_turbulence(h, kmax=0):
+    out = lbm_turbulence_stats()
+    _check(lib().lbm_turbulence(h, int(kmax), ctypes.byref(out)), h)
+    return out.as_dict()
+
+
 def lbm_synchronize(h):
     _check(lib().lbm_synchronize(h), h)
 
@@ -371,6 +395,9 @@ class Lattice:
 
     def structure_functions(self, rs):
         return lbm_structure_functions(self.handle, rs)
+
+    def turbulence(self, kmax=0):
+        return lbm_turbulence(self.handle, kmax)
 
     def save(self):
         return lbm_save_state(self.handle)

@@ -38,3 +38,39 @@ def test_spectrum_and_structure_functions_match_oracle(lbm, shape, precision):
     F4 = S[:, 3] / S[:, 0] ** 2
     print(f"{shape} {precision}: E(1..4) = {E[1:5]}, F4(r) = {np.round(F4, 3)}", flush=True)
     lat.close()
+
+
+@pytest.mark.parametrize("N,precision,tau_mode,rtol", [(32, "fp64", 0, 1e-9), (32, "fp64", 1, 1e-9),
+                                                       (36, "fp32", 0, 2e-4)])
+def test_turbulence_scales_match_oracle(lbm, N, precision, tau_mode, rtol):
+    """lbm_turbulence (Sec. 2.2 scales, energy-balance terms) against the oracle's
+    definitions applied to the GPU's own state (its populations through the
+    oracle's collision for |S| and tau_e)."""
+    from oracle import ref_numpy as R
+    shape = (N, N, N)
+    modes = forced_modes(F0=4e-5, seed=9)
+    tau0, C = 0.507, 0.15
+    lat = lbm.Lattice(shape, tau0, C, modes, precision=precision, smag_form=1,
+                      tau_mode=tau_mode)
+    lat.init(lbm.LBM_INIT_NOISE, 0.02, 17)
+    lat.step(60)
+    f = lat.populations()
+    F = R.force_field(shape, modes)
+    _, info = R.collide(f, F, tau0, C, smag_form=1, tau_mode=tau_mode)
+    nu0 = (tau0 - 0.5) / 3
+    ref = ST.turbulence_scales(info["u"], nu0, snorm=info["Snorm"],
+                               tau_t=info["tau_e"] - tau0, F=F)
+    got = lat.turbulence()
+    assert got["kmax"] == int(0.5 * np.sqrt(3) * N + 1.0)
+    for key in ("energy", "energy_spec", "u_rms", "integral_scale", "eps_spec", "eps_strain",
+                "eps_sgs", "injection", "eta", "taylor", "re_lambda"):
+        assert abs(got[key] - ref[key]) <= rtol * abs(ref[key]), (key, got[key], ref[key])
+    print(f"{N}^3 {precision} tau_mode {tau_mode}: L {got['integral_scale']:.3f}, "
+          f"eta {got['eta']:.3f}, lambda {got['taylor']:.3f}, Re_lambda {got['re_lambda']:.2f}, "
+          f"eps spectral {got['eps_spec']:.3e} / strain {got['eps_strain']:.3e} + sgs "
+          f"{got['eps_sgs']:.3e}, injection {got['injection']:.3e}", flush=True)
+    lat.close()
+    odd = lbm.Lattice((8, 8, 9), tau0, C)
+    with pytest.raises(lbm.LbmError):
+        odd.turbulence()
+    odd.close()

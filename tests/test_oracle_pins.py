@@ -519,3 +519,39 @@ def test_structure_functions_of_a_single_wave():
     v = np.zeros((3, 4, N, 5))
     v[0] = (A * np.sin(2 * np.pi * k * x / N)).reshape(1, N, 1)
     assert np.abs(ST.structure_functions(v, rs)).max() < 1e-15
+
+
+def test_turbulence_scales_of_single_modes():
+    """Sec. 2.2 scales for u_x = A sin(kappa0 y) (+ a second mode): closed forms.
+
+    One mode in shell k0: E(k0) = A^2/4, L = 3 pi / (4 kappa0), u_rms = A / sqrt(6),
+    eps = 2 nu kappa0^2 A^2 / 4, Taylor scale sqrt(5) / kappa0 (independent of A and
+    nu); the real-space 2 nu <S:S> with the exact strain S_xy = A kappa0 cos / 2
+    equals the spectral eps.  Two modes: L is the energy-weighted mean of 1/kappa."""
+    N, A, k0, nu = 16, 0.01, 3, 0.002
+    kap0 = 2 * np.pi * k0 / N
+    y = np.arange(N).reshape(1, N, 1) * np.ones((N, N, N))
+    u = np.zeros((3, N, N, N))
+    u[0] = A * np.sin(kap0 * y)
+    snorm = np.abs(A * kap0 * np.cos(kap0 * y))        # |S| = sqrt(2 S:S) = |A kappa0 cos|
+    F = np.zeros((3, N, N, N))
+    F[0] = 2e-5 * np.sin(kap0 * y)
+    t = ST.turbulence_scales(u, nu, snorm=snorm, tau_t=np.full((N, N, N), 0.003), F=F)
+    assert abs(t["energy_spec"] - A * A / 4) < 1e-18
+    assert abs(t["integral_scale"] - 3 * np.pi / (4 * kap0)) < 1e-12
+    assert abs(t["u_rms"] - A / np.sqrt(6)) < 1e-15
+    assert abs(t["eps_spec"] - 2 * nu * kap0 ** 2 * A * A / 4) < 1e-18
+    assert abs(t["taylor"] - np.sqrt(5) / kap0) < 1e-12
+    assert abs(t["eta"] - (nu ** 3 / t["eps_spec"]) ** 0.25) < 1e-15
+    assert abs(t["eps_strain"] - t["eps_spec"]) < 1e-15 * max(1.0, t["eps_spec"]) + 1e-20
+    assert abs(t["eps_sgs"] - 0.001 * (snorm ** 2).mean()) < 1e-20
+    assert abs(t["injection"] - 2e-5 * A / 2) < 1e-20
+    # a second, weaker mode along z in shell 5
+    k1, B = 5, 0.004
+    kap1 = 2 * np.pi * k1 / N
+    x = np.arange(N).reshape(1, 1, N) * np.ones((N, N, N))
+    u[2] = B * np.cos(kap1 * x)
+    t2 = ST.turbulence_scales(u, nu)
+    E0, E1 = A * A / 4, B * B / 4
+    assert abs(t2["integral_scale"] - 0.75 * np.pi * (E0 / kap0 + E1 / kap1) / (E0 + E1)) < 1e-12
+    assert abs(t2["eps_spec"] - 2 * nu * (kap0 ** 2 * E0 + kap1 ** 2 * E1)) < 1e-18
