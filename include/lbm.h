@@ -154,6 +154,8 @@ typedef struct {
                                  dissipation by the Smagorinsky viscosity     */
     double injection;         /* <F.u>: power injected by the forcing
                                  (eq. energy_balance)                          */
+    double u_mean[3];         /* <u>                                           */
+    double uu[6];             /* <u_i u_j>: xx, yy, zz, xy, xz, yz             */
 } lbm_stats;
 
 /* Fill *cfg with the paper's defaults: 32^3, FP32, AA, tau0 = 0.51, C = 0.1,
@@ -250,6 +252,14 @@ typedef struct {
     double eta;               /* (nu0^3 / eps_spec)^(1/4)                     */
     double taylor;            /* sqrt(15 nu0 u_rms^2 / eps_spec)              */
     double re_lambda;         /* u_rms taylor / nu0                           */
+    /* statistical isotropy (Sec. 3.3) from the Reynolds stresses
+     * R_ij = <u_i u_j> - <u_i><u_j>: directional energy fractions R_ii / R_kk,
+     * anisotropy b_ij = R_ij / R_kk - delta_ij / 3 (xx, yy, zz, xy, xz, yz), its
+     * invariants II_b = -b_ij b_ji / 2, III_b = b_ij b_jk b_ki / 3 and the
+     * Lumley-triangle coordinates xi = (III_b/2)^(1/3) (signed), eta = (-II_b/3)^(1/2) */
+    double energy_frac[3];
+    double b[6];
+    double II_b, III_b, lumley_xi, lumley_eta;
 } lbm_turbulence_stats;
 lbm_status lbm_turbulence(lbm_handle* h, int32_t kmax, lbm_turbulence_stats* out);
 

@@ -115,3 +115,24 @@ def turbulence_scales(u, nu0, snorm=None, tau_t=None, F=None):
     if F is not None:
         out["injection"] = (np.asarray(F) * u).sum(0).mean()
     return out
+
+
+def isotropy(u):
+    """Statistical isotropy of a velocity field u (3, ...) (Sec. 3.3, Fig.
+    isotropy_validation, Tab. isotropy_metrics).
+
+    Reynolds stresses of the fluctuations R_ij = <u'_i u'_j>, directional energy
+    fractions R_ii / R_kk, anisotropy b_ij = R_ij / R_kk - delta_ij / 3, invariants
+    II_b = -b_ij b_ji / 2 and III_b = b_ij b_jk b_ki / 3, Lumley coordinates
+    xi = (III_b / 2)^(1/3) (real cube root), eta = (-II_b / 3)^(1/2).
+    """
+    u = np.asarray(u, dtype=np.float64).reshape(3, -1)
+    up = u - u.mean(axis=1, keepdims=True)
+    R = up @ up.T / up.shape[1]
+    tr = np.trace(R)
+    b = R / tr - np.eye(3) / 3.0
+    II = -0.5 * np.trace(b @ b)
+    III = np.trace(b @ b @ b) / 3.0
+    return dict(energy_frac=np.diag(R) / tr,
+                b=np.array([b[0, 0], b[1, 1], b[2, 2], b[0, 1], b[0, 2], b[1, 2]]),
+                II_b=II, III_b=III, lumley_xi=np.cbrt(III / 2.0), lumley_eta=np.sqrt(-II / 3.0))

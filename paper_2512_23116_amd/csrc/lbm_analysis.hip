@@ -265,6 +265,29 @@ lbm_status lbm_turbulence(lbm_handle* h, int32_t kmax, lbm_turbulence_stats* out
     out->eta = eps > 0.0 ? pow(nu0 * nu0 * nu0 / eps, 0.25) : NAN;          // eq. kolmogorov_scale
     out->taylor = eps > 0.0 ? sqrt(15.0 * nu0 * out->u_rms * out->u_rms / eps) : NAN;  // eq. taylor_microscale
     out->re_lambda = out->u_rms * out->taylor / nu0;
+    // isotropy: Reynolds stresses of the fluctuations about the mean velocity
+    const double* m = s.u_mean;
+    const double R[3][3] = {
+        {s.uu[0] - m[0] * m[0], s.uu[3] - m[0] * m[1], s.uu[4] - m[0] * m[2]},
+        {s.uu[3] - m[0] * m[1], s.uu[1] - m[1] * m[1], s.uu[5] - m[1] * m[2]},
+        {s.uu[4] - m[0] * m[2], s.uu[5] - m[1] * m[2], s.uu[2] - m[2] * m[2]}};
+    const double tr = R[0][0] + R[1][1] + R[2][2];
+    double b[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) b[i][j] = tr > 0.0 ? R[i][j] / tr - (i == j ? 1.0 / 3.0 : 0.0) : NAN;
+    double b2 = 0.0, b3 = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            b2 += b[i][j] * b[j][i];
+            for (int k = 0; k < 3; ++k) b3 += b[i][j] * b[j][k] * b[k][i];
+        }
+    for (int i = 0; i < 3; ++i) out->energy_frac[i] = tr > 0.0 ? R[i][i] / tr : NAN;
+    out->b[0] = b[0][0]; out->b[1] = b[1][1]; out->b[2] = b[2][2];
+    out->b[3] = b[0][1]; out->b[4] = b[0][2]; out->b[5] = b[1][2];
+    out->II_b = -0.5 * b2;
+    out->III_b = b3 / 3.0;
+    out->lumley_xi = cbrt(0.5 * out->III_b);
+    out->lumley_eta = sqrt(fmax(0.0, -out->II_b / 3.0));
     return LBM_OK;
 }
 

@@ -434,7 +434,7 @@ lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out) {
                                result, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "diagnostic kernel");
     double r[kDiagSlots];
-    HIPCHK(h, hipMemcpyAsync(r, result, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(r, result, 25 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     lbm_status st = sync(h);
     if (st != LBM_OK) return st;
 
@@ -474,6 +474,8 @@ lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out) {
     out->strain2 = r[13] / n;
     out->nut_strain2 = r[14] / (3.0 * n);   // nu_t = tau_t / 3
     out->injection = r[15] / n;
+    for (int a = 0; a < 3; ++a) out->u_mean[a] = r[16 + a] / n;
+    for (int a = 0; a < 6; ++a) out->uu[a] = r[19 + a] / n;
     if (out->n_nonfinite > 0)
         return fail(h, LBM_ERR_UNSTABLE, "%lld non-finite cells", (long long)out->n_nonfinite);
     return LBM_OK;

@@ -71,7 +71,7 @@ bool tb2_supported(int precision);
 hipError_t launch_step_tb2(int precision, const LatticeArgs& L, hipStream_t s);
 
 constexpr int kDiagBlocks = 1024;   // fixed grid of the diagnostic reduction
-constexpr int kDiagSlots = 16;      // doubles per block partial
+constexpr int kDiagSlots = 32;      // doubles per block partial
 
 }  // namespace lbm
 

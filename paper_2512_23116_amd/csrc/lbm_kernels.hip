@@ -30,8 +30,9 @@ __global__ __launch_bounds__(256) void k_step(LatticeArgs L) {
 // Per-block FP64 partials: [0..3] sum of tau_t^p (p = 1..4, tau_t = tau_e - tau0),
 // [4] min tau_t, [5] max tau_t, [6] sum delta rho, [7..9] sum rho u,
 // [10] sum u.u/2, [11] sum rho u.u/2, [12] non-finite cells, [13] sum |S|^2,
-// [14] sum tau_t |S|^2 (3 nu_t |S|^2), [15] sum F.u (power injected, eq. energy_balance).
-constexpr int kDiagUsed = 16;
+// [14] sum tau_t |S|^2 (3 nu_t |S|^2), [15] sum F.u (power injected, eq. energy_balance),
+// [16..18] sum u_i, [19..24] sum u_i u_j (xx, yy, zz, xy, xz, yz; Reynolds stresses).
+constexpr int kDiagUsed = 25;
 static_assert(kDiagUsed <= kDiagSlots, "diagnostic partials overflow their slots");
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -88,8 +89,11 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
         const double s2 = (double)m.snorm2;
         acc[13] += s2; acc[14] += tt * s2;
         acc[15] += (double)Fx * ux + (double)Fy * uy + (double)Fz * uz;
+        acc[16] += ux; acc[17] += uy; acc[18] += uz;
+        acc[19] += ux * ux; acc[20] += uy * uy; acc[21] += uz * uz;
+        acc[22] += ux * uy; acc[23] += ux * uz; acc[24] += uy * uz;
     }
-    __shared__ double red[4][16];
+    __shared__ double red[4][kDiagUsed];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < kDiagUsed; ++j) {
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
     }
 }
 
-// Reduce the per-block partials in a fixed order into result[0..15].
+// Reduce the per-block partials in a fixed order into result[0..kDiagUsed).
 __global__ __launch_bounds__(256) void k_diag_final(const double* partials, int nblocks,
                                                     double* result) {
     __shared__ double red[256];

@@ -75,13 +75,14 @@ class lbm_stats(ctypes.Structure):
         ("n_nonfinite", ctypes.c_int64),
         ("strain2", ctypes.c_double), ("nut_strain2", ctypes.c_double),
         ("injection", ctypes.c_double),
+        ("u_mean", ctypes.c_double * 3), ("uu", ctypes.c_double * 6),
     ]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            out[name] = list(v) if name == "momentum" else v
+            out[name] = list(v) if name in ("momentum", "u_mean", "uu") else v
         return out
 
 
@@ -93,10 +94,18 @@ class lbm_turbulence_stats(ctypes.Structure):
         ("eps_spec", ctypes.c_double), ("eps_strain", ctypes.c_double),
         ("eps_sgs", ctypes.c_double), ("injection", ctypes.c_double),
         ("eta", ctypes.c_double), ("taylor", ctypes.c_double), ("re_lambda", ctypes.c_double),
+        ("energy_frac", ctypes.c_double * 3), ("b", ctypes.c_double * 6),
+        ("II_b", ctypes.c_double), ("III_b", ctypes.c_double),
+        ("lumley_xi", ctypes.c_double), ("lumley_eta", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+        out = {}
+        for name, _ in self._fields_:
+            if name != "pad":
+                v = getattr(self, name)
+                out[name] = list(v) if name in ("energy_frac", "b") else v
+        return out
 
 
 class LbmError(RuntimeError):

@@ -1,4 +1,5 @@
-"""Energy balance of forced HIT (Sec. 2.2 eq. energy_balance, Sec. 3.2).
+"""Energy balance and statistical isotropy of forced HIT (Sec. 2.2 eq. energy_balance,
+Sec. 3.2, Sec. 3.3).
 
 The paper checks eps = -dE_k/dt + <F.u> in real space for DNS at Re = 2500 on
 128^3 and 256^3 and reports the relative error settling, after t/t0 = 200, near
@@ -11,7 +12,10 @@ Every `every` steps the device returns E_k = 1/2 <u.u>, <F.u>, the dissipation
 from the strain of the non-equilibrium moments eps_strain = 2 nu0 <S:S>, and the
 spectral eps = 2 nu0 sum kappa^2 E(k) (lbm_turbulence).  dE_k/dt is the central
 difference of E_k over the neighbouring snapshots.  Relative error:
-|eps - (<F.u> - dE_k/dt)| / eps, averaged over the window.
+|eps - (<F.u> - dE_k/dt)| / eps, averaged over the window.  Isotropy (Sec. 3.3,
+Tab. isotropy_metrics): mean and standard deviation of the directional energy
+fractions E_i / E and the mean |b_ij| of the off-diagonal anisotropy over the
+window, from the Reynolds stresses lbm_turbulence returns.
 
     python -m paper_2512_23116_amd.studies.energy_balance [--N 128] [--t-end 400]
 """
@@ -47,7 +51,8 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         tb = lat.turbulence()
         rows.append(dict(step=step, E=tb["energy"], P=tb["injection"],
                          eps_strain=tb["eps_strain"], eps_spec=tb["eps_spec"],
-                         re_lambda=tb["re_lambda"], eta=tb["eta"]))
+                         re_lambda=tb["re_lambda"], eta=tb["eta"],
+                         frac=tb["energy_frac"], b=tb["b"]))
         if len(rows) % 50 == 0:
             log(f"energy balance {N}^3: t/t0 = {step / t0:g}, {time.time() - tic:.1f} s")
     lat.close()
@@ -59,13 +64,16 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         out.append(dict(t=r["step"] / t0, E=r["E"], P=r["P"], dEdt=dEdt,
                         err_strain=abs(r["eps_strain"] - bal) / r["eps_strain"],
                         err_spec=abs(r["eps_spec"] - bal) / r["eps_spec"],
-                        re_lambda=r["re_lambda"], eta=r["eta"]))
+                        re_lambda=r["re_lambda"], eta=r["eta"], frac=r["frac"], b=r["b"]))
     summary = dict(
         N=N, Re=Re, tau0=tau0, F0=F0, window=[t_start, t_end], snapshots=len(out),
         mean_err_eps_strain=float(np.mean([o["err_strain"] for o in out])),
         mean_err_eps_spec=float(np.mean([o["err_spec"] for o in out])),
         mean_re_lambda=float(np.mean([o["re_lambda"] for o in out])),
         mean_eta=float(np.mean([o["eta"] for o in out])),
+        energy_frac_mean=[float(v) for v in np.mean([o["frac"] for o in out], axis=0)],
+        energy_frac_std=[float(v) for v in np.std([o["frac"] for o in out], axis=0)],
+        mean_abs_b_offdiag=[float(v) for v in np.mean([np.abs(o["b"][3:]) for o in out], axis=0)],
         paper_err={128: "6-7 %", 256: "< 3.5 %", 512: "~1 % (Re 5000)"}.get(N),
         wall_s=time.time() - tic)
     return summary, out

@@ -65,10 +65,18 @@ def test_turbulence_scales_match_oracle(lbm, N, precision, tau_mode, rtol):
     for key in ("energy", "energy_spec", "u_rms", "integral_scale", "eps_spec", "eps_strain",
                 "eps_sgs", "injection", "eta", "taylor", "re_lambda"):
         assert abs(got[key] - ref[key]) <= rtol * abs(ref[key]), (key, got[key], ref[key])
+    iso = ST.isotropy(info["u"])
+    # b and the fractions are O(1) quantities: compare absolutely
+    np.testing.assert_allclose(got["energy_frac"], iso["energy_frac"], rtol=0, atol=rtol)
+    np.testing.assert_allclose(got["b"], iso["b"], rtol=0, atol=rtol)
+    for key in ("II_b", "III_b", "lumley_xi", "lumley_eta"):
+        assert abs(got[key] - iso[key]) <= 10 * rtol * max(1e-3, abs(iso[key])), (key, got[key], iso[key])
     print(f"{N}^3 {precision} tau_mode {tau_mode}: L {got['integral_scale']:.3f}, "
           f"eta {got['eta']:.3f}, lambda {got['taylor']:.3f}, Re_lambda {got['re_lambda']:.2f}, "
           f"eps spectral {got['eps_spec']:.3e} / strain {got['eps_strain']:.3e} + sgs "
-          f"{got['eps_sgs']:.3e}, injection {got['injection']:.3e}", flush=True)
+          f"{got['eps_sgs']:.3e}, injection {got['injection']:.3e}, energy fractions "
+          f"{np.round(got['energy_frac'], 4)}, Lumley ({got['lumley_xi']:.4f}, "
+          f"{got['lumley_eta']:.4f})", flush=True)
     lat.close()
     odd = lbm.Lattice((8, 8, 9), tau0, C)
     with pytest.raises(lbm.LbmError):

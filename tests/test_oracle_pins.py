@@ -555,3 +555,26 @@ def test_turbulence_scales_of_single_modes():
     E0, E1 = A * A / 4, B * B / 4
     assert abs(t2["integral_scale"] - 0.75 * np.pi * (E0 / kap0 + E1 / kap1) / (E0 + E1)) < 1e-12
     assert abs(t2["eps_spec"] - 2 * nu * (kap0 ** 2 * E0 + kap1 ** 2 * E1)) < 1e-18
+
+
+def test_isotropy_invariants_hit_the_lumley_vertices():
+    """Textbook states of the anisotropy invariant map: isotropic (0, 0), one-component
+    (1/3, 1/3), two-component axisymmetric (-1/6, 1/6); energy fractions and b."""
+    rng = np.random.default_rng(12)
+    n = 200000
+    a, c, d = rng.standard_normal((3, n))
+    z = np.zeros(n)
+    iso = ST.isotropy(np.stack([a, c, d]) + 0.3)           # a constant mean is removed
+    assert abs(iso["lumley_xi"]) < 0.03 and abs(iso["lumley_eta"]) < 0.03
+    np.testing.assert_allclose(iso["energy_frac"], [1 / 3] * 3, atol=0.01)
+    one = ST.isotropy(np.stack([a, z, z]))
+    assert abs(one["lumley_xi"] - 1 / 3) < 1e-12 and abs(one["lumley_eta"] - 1 / 3) < 1e-12
+    np.testing.assert_allclose(one["b"][:3], [2 / 3, -1 / 3, -1 / 3], atol=1e-14)
+    np.testing.assert_allclose(one["energy_frac"], [1, 0, 0], atol=1e-14)
+    th = 2 * np.pi * np.arange(n) / n          # <cos^2> = <sin^2> = 1/2, <cos sin> = 0
+    two = ST.isotropy(np.stack([np.cos(th), np.sin(th), z]))
+    assert abs(two["lumley_xi"] + 1 / 6) < 1e-12 and abs(two["lumley_eta"] - 1 / 6) < 1e-12
+    np.testing.assert_allclose(two["b"], [1 / 6, 1 / 6, -1 / 3, 0, 0, 0], atol=1e-12)
+    # an off-diagonal stress: u_y = u_x gives b_xy = 1/2, II_b = -1/3 ... realizable
+    sh = ST.isotropy(np.stack([a, a, z]))
+    assert abs(sh["b"][3] - 0.5) < 1e-12 and sh["lumley_eta"] <= 1 / 3 + 1e-12
