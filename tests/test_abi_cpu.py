@@ -115,3 +115,30 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(m, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         m.lib()
+
+
+def test_null_handles_are_rejected_without_touching_a_device(lbm):
+    """Every handle-taking entry point returns INVALID_ARG for NULL (no GPU needed)."""
+    import numpy as np
+    L = lbm.lib()
+    d = np.zeros(64)
+    dp = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = lbm.lbm_stats()
+    ts = lbm.lbm_turbulence_stats()
+    rs = (ctypes.c_int32 * 1)(1)
+    calls = [
+        lambda: L.lbm_init_seeded(None, 0, 0.0, 0),
+        lambda: L.lbm_step(None, 1),
+        lambda: L.lbm_moments(None, dp, dp),
+        lambda: L.lbm_kt_stats(None, ctypes.byref(st)),
+        lambda: L.lbm_get_populations(None, dp),
+        lambda: L.lbm_set_populations(None, dp),
+        lambda: L.lbm_spectrum(None, 4, dp),
+        lambda: L.lbm_structure_functions(None, rs, 1, dp),
+        lambda: L.lbm_turbulence(None, 0, ctypes.byref(ts)),
+        lambda: L.lbm_synchronize(None),
+    ]
+    for call in calls:
+        assert call() == lbm.LBM_ERR_INVALID_ARG
+    assert L.lbm_steps_done(None) == -1 and L.lbm_num_cells(None) == -1
+    L.lbm_destroy(None)
