@@ -49,8 +49,14 @@ typedef const LBM_CONSTANT_SPACE BatchTable ConstTable;
 __global__ __launch_bounds__(256) void k_batch_step(const BatchTable* tab_generic, int k) {
     ConstTable* tab = (ConstTable*)tab_generic;
     const uint32_t ns = tab->n_slots, total = tab->total_tiles;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        uint32_t s = 0;
+    // Consecutive workgroups are dispatched round-robin over the 8 XCDs: give each
+    // XCD one contiguous eighth of the tile space (its L2 then holds neighbouring
+    // planes), walked by that XCD's workgroups in turn.  The grid is a multiple of 8.
+    const uint32_t xcd = blockIdx.x & 7u, per = gridDim.x >> 3;
+    const uint32_t t_end = (uint32_t)(((uint64_t)total * (xcd + 1u)) >> 3);
+    uint32_t s = 0;   // tiles only increase along the loop, so the slot does too
+    for (uint32_t t = (uint32_t)(((uint64_t)total * xcd) >> 3) + (blockIdx.x >> 3); t < t_end;
+         t += per) {
         while (s + 1 < ns && tab->slot[s + 1].tile_begin <= t) ++s;
         if ((uint32_t)k >= tab->slot[s].nsteps) continue;
         const uint32_t cell = (t - tab->slot[s].tile_begin) * 256u + threadIdx.x;
@@ -159,7 +165,7 @@ lbm_status lbm_batch_create(int32_t max_slots, int32_t steps_per_graph, void* hi
         lbm_batch_destroy(b);
         return e == hipErrorOutOfMemory ? LBM_ERR_OUT_OF_MEMORY : LBM_ERR_DEVICE;
     }
-    b->grid = std::max(1, cus) * 8;
+    b->grid = std::max(1, cus) * 8;   // a multiple of 8 (the kernel splits it per XCD)
     memset(b->h_table, 0, b->table_bytes);
     *out = b;
     return LBM_OK;
