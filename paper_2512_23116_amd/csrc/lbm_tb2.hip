@@ -63,6 +63,8 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     __shared__ R down[5][TB_E];      // c_z = -1 populations of plane z+1
     __shared__ R mid[2][9][TB_E];    // c_z =  0 populations, planes z+1 and z
     __shared__ R up[3][5][TB_E];     // c_z = +1 populations, planes z+1, z, z-1
+    __shared__ R rowbuf[2][TB_EY][16];  // force row coefficients of the phase-1 plane, per tile row
+    __shared__ R xbuf[TB_EX][4];        // x harmonics of the tile columns
 
     const LatticeArgs& L = A.L;
     uint32_t b = blockIdx.x;
@@ -107,22 +109,56 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
         load_cell<Cd, PAT_AB>(src, x1 + L.nx * p.row, nb, g, inv_s);
     };
 
+    // Force (eq. forcing_pattern via the row / x-harmonic tables).  With 16-bit
+    // storage the row coefficients of the next phase-1 plane are fetched one
+    // iteration ahead into LDS by the first 16 * TB_EY threads (one value each:
+    // tile row r, coefficient e) and the x harmonics of the 64 columns sit in LDS,
+    // so phase 1 waits on no table load (+9 % at 800^3).  With FP32 storage that
+    // costs more than it saves (-7 %): phase 1 reads the tables directly.
+    constexpr bool kLdsRows = sizeof(T) == 2;
+    const bool forced = L.rowc != nullptr;
+    const R* rowc = (const R*)L.rowc;
+    const int rr = t >> 4, re = t & 15;           // for t < 16 * TB_EY
+    const bool row_loader = kLdsRows && forced && t < 16 * TB_EY;
+    const uint32_t ry = wrap_add(Y0, rr - 1, L.ny);
+    auto row_coeff = [&](int j) { return rowc[(uint64_t)(ry + L.ny * plane1(j)) * 16 + re]; };
+    if (kLdsRows) {
+        if (forced && t < 4 * TB_EX)
+            xbuf[t >> 2][t & 3] =
+                ((const R*)L.xtab)[(uint64_t)wrap_add(X0, (t >> 2) - 1, L.nx) * 4 + (t & 3)];
+        if (row_loader) rowbuf[0][rr][re] = row_coeff(0);
+        __syncthreads();
+    }
+
     // One iteration j: phase 1 on the prefetched pulls P of plane Z0 - 1 + j,
     // then the pulls of plane j + 2 are issued into P (two planes of prefetch
     // in flight), then phase 2 on plane Z0 + j - 2.
     const int niter = nzc + 2;
+    // The phase-2 cell of iteration j is the phase-1 cell of iteration j - 1 (same
+    // column, plane Z0 + j - 2): its force is carried over instead of recomputed.
+    R Fpx = R(0), Fpy = R(0), Fpz = R(0);
     auto iteration = [&](int j, R (&P)[19]) {
+        R Fx = R(0), Fy = R(0), Fz = R(0);
         {   // phase 1: step t at plane Z0 - 1 + j for every extended column
             R g[19];
 #pragma unroll
             for (int i = 0; i < 19; ++i) g[i] = P[i];
-            CellPos p;
-            p.x = x1;
-            p.y = y1;
-            p.z = plane1(j);
-            p.row = y1 + L.ny * p.z;
-            R Fx, Fy, Fz;
-            force_at<R>(L, p, Fx, Fy, Fz);
+            if constexpr (kLdsRows) {
+                if (forced) {
+                    const R* rc = rowbuf[j & 1][ey];
+                    const R s1 = xbuf[ex][0], c1 = xbuf[ex][1], s2 = xbuf[ex][2], c2 = xbuf[ex][3];
+                    Fx = rc[0] + s1 * rc[3] + c1 * rc[6] + s2 * rc[9] + c2 * rc[12];
+                    Fy = rc[1] + s1 * rc[4] + c1 * rc[7] + s2 * rc[10] + c2 * rc[13];
+                    Fz = rc[2] + s1 * rc[5] + c1 * rc[8] + s2 * rc[11] + c2 * rc[14];
+                }
+            } else {
+                CellPos p;
+                p.x = x1;
+                p.y = y1;
+                p.z = plane1(j);
+                p.row = y1 + L.ny * p.z;
+                force_at<R>(L, p, Fx, Fy, Fz);
+            }
             collide<R, true>(g, Fx, Fy, Fz, k);
             const int s2 = j & 1, s3 = j % 3;
             static_for<19>([&](auto I) {
@@ -135,6 +171,10 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
             });
         }
         __syncthreads();
+        // (16-bit storage) the next plane's row coefficients, before the pulls
+        R rnext = R(0);
+        const bool fetch = row_loader && j + 1 < niter;
+        if (fetch) rnext = row_coeff(j + 1);
         if (j + 2 < niter) pull(j + 2, P);
         if (j >= 2 && inner) {   // phase 2: step t+1 at plane Z0 + j - 2
             const uint32_t z2 = Z0 + (uint32_t)(j - 2);
@@ -148,20 +188,17 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
                 else if constexpr (cz == 0) g[i] = mid[s2][ii][col]; // from plane z2
                 else g[i] = up[s3][ii][col];                         // from plane z2 - 1
             });
-            CellPos p;
-            p.x = x2;
-            p.y = y2;
-            p.z = z2;
-            p.row = y2 + L.ny * z2;
-            R Fx, Fy, Fz;
-            force_at<R>(L, p, Fx, Fy, Fz);
-            collide<R, true>(g, Fx, Fy, Fz, k);
-            const uint32_t cell = x2 + L.nx * p.row;
+            collide<R, true>(g, Fpx, Fpy, Fpz, k);
+            const uint32_t cell = x2 + L.nx * (y2 + L.ny * z2);
             static_for<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 *elem_ptr<T>(dst, i, cell) = enc<Cd>(g[i], s_st);
             });
         }
+        if (fetch) rowbuf[(j + 1) & 1][rr][re] = rnext;   // read after the next barrier
+        Fpx = Fx;
+        Fpy = Fy;
+        Fpz = Fz;
         __syncthreads();
     };
 
@@ -177,7 +214,7 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
 bool tb2_supported(int precision) { return precision != LBM_FP64; }
 
 hipError_t launch_step_tb2(int precision, const LatticeArgs& L, hipStream_t s) {
-    // 64 x 16 extended tiles: one 1024-thread workgroup and 152 KB of LDS per CU.
+    // 64 x 16 extended tiles: one 1024-thread workgroup and 152-155 KB of LDS per CU.
     // (64 x 8 tiles, two workgroups per CU, measured 25 % slower at 800^3.)
     constexpr int EY = 16;
     TB2Args A;
