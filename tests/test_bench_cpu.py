@@ -1,0 +1,29 @@
+"""bench.py contract pieces that need no GPU."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_counter_traffic_is_keyed_by_kernel_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert rows, "no counter rows"
+    for key, sha, fetch, write, fam, *_ in rows:
+        got = bench.counter_traffic(key, fam)
+        if sha == kernel_source_sha(fam):
+            assert got == float(fetch) + float(write)
+        else:
+            assert got is None
+    assert bench.counter_traffic("no_such_lattice") is None
