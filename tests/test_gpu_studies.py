@@ -38,3 +38,14 @@ def test_energy_balance_study_small():
     for r in rows:
         assert r["E"] > 0 and r["P"] > 0 and math.isfinite(r["dEdt"])
     assert summary["mean_err_eps_strain"] < 0.2, summary
+
+
+def test_intermittency_study_small():
+    """Short LES run on 48^3: F_4 is finite and above 3 at the smallest separation,
+    and the ESS exponents increase with p."""
+    from paper_2512_23116_amd.studies import intermittency
+    res = intermittency.run("les", t_start=10, t_end=12, every=1000, N=48, log=lambda m: None)
+    assert res["snapshots"] == 3
+    assert all(math.isfinite(v) for v in res["F4"]) and res["F4"][0] > 3.0
+    z = res["zeta"]
+    assert z[2] < z[4] < z[5] < z[6]
