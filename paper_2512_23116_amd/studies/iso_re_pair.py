@@ -1,0 +1,137 @@
+"""Iso-Reynolds DNS/LES pair (Sec. 3.1, Sec. 5.2-5.3), at half the paper's size.
+
+The paper pairs a DNS on 800^3 (tau0 - 1/2 = 5.16e-3) with an LES on 100^3
+(tau0 - 1/2 = 6.45e-4, C = 0.13): same U0 = 0.043, grid ratio 8, viscosity
+scaled with the grid so Re = U0 N / nu0 = 2e4 for both.  Here the same two
+relaxation times run on 400^3 (DNS, C = 0) and 50^3 (LES): grid ratio 8,
+Re = 1e4 for both.  Three-mode forcing of eq. forcing_pattern with
+F0 = C_f U0^2 / N, Taylor-Green start of amplitude U0, t0 = 1000 steps.
+
+Over the window [t_start, t_end] (units of t0) every `every` steps the device
+returns E(k), the turbulence scales (lbm_turbulence) and the structure
+functions; the study reports the time-averaged spectrum in Kolmogorov units
+(kappa eta, E(kappa) / (eps nu^5)^(1/4), with kappa = 2 pi k / N, E(kappa) the
+shell energy divided by the shell width 2 pi / N, nu the molecular
+viscosity and eps the injected power <F.u>, which equals the total dissipation
+in the steady window), the flatness F4(r)
+against r / eta, the ESS exponents, and for the LES the statistics of
+theta = tau_e - 1/2 (Sec. 5.1).
+
+    python -m paper_2512_23116_amd.studies.iso_re_pair [--scale 2] [--t-end 300]
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+ORDERS = {2: 0, 4: 3, 5: 4, 6: 5}
+
+
+def one_run(kind, N, tau0, C, t_start, t_end, every, log):
+    import torch
+    from .. import lbm, params
+    from ..inputs import paper_modes
+    stream = torch.cuda.Stream()
+    tb = 2 if kind == "dns" else 0
+    lat = lbm.Lattice((N, N, N), tau0, C, paper_modes(params.forcing_amplitude(N)),
+                      precision="fp32", streaming="ab" if tb else "aa", smag_form=1,
+                      steps_per_graph=64, temporal_block=tb, stream=stream)
+    lat.init(lbm.LBM_INIT_TGV3D, params.U0)
+    t0 = 1000
+    tic = time.time()
+    chunk = 25 * t0
+    while lat.steps < t_start * t0:
+        lat.step(min(chunk, t_start * t0 - lat.steps))
+        lat.sync()
+        log(f"{kind} {N}^3: t/t0 = {lat.steps / t0:g}, {time.time() - tic:.0f} s")
+    rs = sorted(set(int(r) for r in np.round(np.geomspace(1, N // 2, 14))))
+    kmax = N // 2
+    E = np.zeros(kmax + 1)
+    S = np.zeros((len(rs), 6))
+    scales = []
+    th = []
+    n = 0
+    for step in range(t_start * t0, t_end * t0 + 1, every):
+        if step > lat.steps:
+            lat.step(step - lat.steps)
+        E += lat.spectrum(kmax)
+        S += lat.structure_functions(rs)
+        tb_ = lat.turbulence()
+        scales.append(tb_)
+        if C > 0:
+            st = lat.stats()
+            th.append((st["theta_mean"], st["theta_var"], st["theta_min"], st["theta_max"]))
+        n += 1
+        if n % 25 == 0:
+            log(f"{kind} {N}^3: window t/t0 = {step / t0:g}, {time.time() - tic:.0f} s")
+    lat.close()
+    E /= n
+    S /= n
+    nu0 = (tau0 - 0.5) / 3.0
+    # the dissipation that sets the Kolmogorov units is the total one, which in the
+    # statistically steady window equals the injected power <F.u>; the LES resolves
+    # only part of it with nu0 (the rest goes through nu_t), so 2 nu0 sum kappa^2 E
+    # would not do for it
+    eps = float(np.mean([s["injection"] for s in scales]))
+    eta = (nu0 ** 3 / eps) ** 0.25
+    k = np.arange(kmax + 1)
+    kap = 2 * np.pi * k / N
+    out = dict(kind=kind, N=N, tau0=tau0, C=C, Re=0.043 * N / nu0, snapshots=n,
+               eps=eps, eps_spec=float(np.mean([s["eps_spec"] for s in scales])),
+               eps_strain_plus_sgs=float(np.mean([s["eps_strain"] + s["eps_sgs"] for s in scales])),
+               eta=eta, re_lambda=float(np.mean([s["re_lambda"] for s in scales])),
+               k_eta=[float(v) for v in kap[1:] * eta],
+               # E(kappa) = shell energy / shell width 2 pi / N
+               E_kolmogorov=[float(v) for v in E[1:] * N / (2 * np.pi) / (eps * nu0 ** 5) ** 0.25],
+               r_over_eta=[float(r / eta) for r in rs],
+               F4=[float(v) for v in S[:, 3] / S[:, 0] ** 2], wall_s=time.time() - tic)
+    lo, hi = max(2, int(3 * N / 100)), max(6, int(12 * N / 100))
+    sel = [i for i, r in enumerate(rs) if lo <= r <= hi]
+    x = np.log(S[sel, 2])
+    out["zeta"] = {p: float(np.polyfit(x, np.log(S[sel, c]), 1)[0]) for p, c in ORDERS.items()}
+    out["r_fit"] = [lo, hi]
+    if th:
+        a = np.array(th)
+        out["theta_mean"] = float(a[:, 0].mean())
+        out["theta_var"] = float(a[:, 1].mean())
+        out["theta_min"] = float(a[:, 2].min())
+        out["theta_max"] = float(a[:, 3].max())
+        out["theta_mean_over_theta0"] = out["theta_mean"] / (tau0 - 0.5)
+    return out
+
+
+def run(scale=2, t_start=200, t_end=300, every=1000,
+        log=lambda m: print(m, file=sys.stderr, flush=True)):
+    """scale = 800 / N_DNS: 1 is the paper's pair (800^3 / 100^3), 2 is 400^3 / 50^3."""
+    from .. import params
+    N_dns, N_les = 800 // scale, 100 // scale
+    Re = 2.0e4 / scale
+    tau_dns = params.tau0_from_re(N_dns, Re)       # 0.5 + 5.16e-3 for any scale
+    tau_les = params.tau0_from_re(N_les, Re)       # 0.5 + 6.45e-4
+    les = one_run("les", N_les, tau_les, 0.13, t_start, t_end, every, log)
+    dns = one_run("dns", N_dns, tau_dns, 0.0, t_start, t_end, every, log)
+    # the LES spectrum on the DNS's k eta grid (Kolmogorov units, log interpolation)
+    kd, Ed = np.array(dns["k_eta"]), np.array(dns["E_kolmogorov"])
+    kl, El = np.array(les["k_eta"]), np.array(les["E_kolmogorov"])
+    m = (kd >= kl[0]) & (kd <= kl[-1])
+    ratio = np.exp(np.interp(np.log(kd[m]), np.log(kl), np.log(El)) - np.log(Ed[m]))
+    return dict(scale=scale, Re=Re, window=[t_start, t_end], les=les, dns=dns,
+                les_over_dns_spectrum=dict(k_eta=[float(v) for v in kd[m]],
+                                           ratio=[float(v) for v in ratio]))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--scale", type=int, default=2)
+    ap.add_argument("--t-start", type=int, default=200)
+    ap.add_argument("--t-end", type=int, default=300)
+    ap.add_argument("--every", type=int, default=1000)
+    a = ap.parse_args()
+    print(json.dumps(run(a.scale, a.t_start, a.t_end, a.every)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,3 +49,16 @@ def test_intermittency_study_small():
     assert all(math.isfinite(v) for v in res["F4"]) and res["F4"][0] > 3.0
     z = res["zeta"]
     assert z[2] < z[4] < z[5] < z[6]
+
+
+def test_iso_re_pair_study_small():
+    """The DNS/LES pair at 1/16 of the paper's size (50^3 / 6^3), short window:
+    both runs report finite Kolmogorov-scaled spectra, F4 and ESS exponents."""
+    from paper_2512_23116_amd.studies import iso_re_pair
+    res = iso_re_pair.run(scale=16, t_start=2, t_end=3, every=500, log=lambda m: None)
+    for kind in ("les", "dns"):
+        r = res[kind]
+        assert r["snapshots"] == 3 and r["eps"] > 0 and r["eta"] > 0
+        assert all(math.isfinite(v) and v > 0 for v in r["E_kolmogorov"])
+        assert all(math.isfinite(v) for v in r["F4"])
+    assert res["les"]["theta_min"] > 0
