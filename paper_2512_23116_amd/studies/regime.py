@@ -8,7 +8,7 @@ t/t0 in [200, 600], a domain-mean offset of about 1.34e-3 with the 95th
 percentile below about 1.82e-3, the 5th above 1.0e-3 and no negative values
 (Sec. 5.1, Fig. tau_timeseries).
 
-    python -m paper_2512_23116_amd.studies.regime [--smag-form 0|1] [--t-end 1000]
+    python -m paper_2512_23116_amd.studies.regime [--smag-form 0|1] [--t-end 600]
 
 Per snapshot the K_t field comes back from the device (lbm_kt_field) and the
 host takes the domain mean and percentiles of theta = K_t / sqrt(3); the run
@@ -23,7 +23,7 @@ import time
 import numpy as np
 
 
-def run(smag_form=0, C=0.13, t_start=200, t_end=1000, every=2000, N=100, amp=None,
+def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None,
         log=lambda m: print(m, file=sys.stderr, flush=True)):
     import torch
     from .. import lbm, params
@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--smag-form", type=int, default=0)
     ap.add_argument("--C", type=float, default=0.13)
     ap.add_argument("--t-start", type=int, default=200)
-    ap.add_argument("--t-end", type=int, default=1000)
+    ap.add_argument("--t-end", type=int, default=600)
     ap.add_argument("--every", type=int, default=2000)
     a = ap.parse_args()
     import torch
