@@ -217,7 +217,9 @@ lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n
  * for integer shells k = 0..kmax (0 <= kmax <= 4096), u the velocity with the
  * half-force shift of eq. guo_velocity.  FP64 FFT (hipFFT) on the device; the
  * shell sums use LDS atomics, so the last bits may vary between calls.  Host
- * double[kmax+1].  Allocates device temporaries (~ncells * 40 bytes).
+ * double[kmax+1].  The first call creates the FFT plan and device buffers
+ * (~32 bytes per cell plus kmax-sized partial sums) that the handle keeps for
+ * later analysis calls until lbm_destroy.
  * Synchronises. */
 lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
 
@@ -226,7 +228,8 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
  *   out[6 j + m] = mean over cells x and axes a of p_m(du),
  *   du = u_a(x + r e_a) - u_a(x) (periodic),  p = (du^2, du^3, |du|^3, du^4, |du|^5, du^6).
  * F4(r) = out[6j+3] / out[6j]^2.  FP64, reduced in a fixed order (bitwise
- * reproducible).  nr in 1..65535.  Allocates device temporaries.  Synchronises. */
+ * reproducible).  nr in 1..65535.  Uses the handle's analysis velocity buffer
+ * (created on first use, 24 bytes per cell) and temporaries.  Synchronises. */
 lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr, double* out);
 
 /* Turbulence scales of the current state (Sec. 2.2, eq. integral_length_scale,

@@ -140,14 +140,68 @@ lbm_status hip_err(lbm_handle* h, hipError_t e, const char* what) {
                    std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Velocity (FP64, [3][ncell]) of the current state into a new device buffer.
-lbm_status velocity(lbm_handle* h, DevBuf& u) {
+}  // namespace
+
+namespace lbm {
+
+struct AnalysisCache {
+    double* u = nullptr;                  // [3][ncell] velocity, FP64
+    hipfftDoubleComplex* c = nullptr;     // [nz][ny][nx/2+1] transform of one component
+    size_t c_elems = 0;
+    double* part = nullptr;               // per-block partial sums
+    size_t part_elems = 0;
+    double* out = nullptr;                // reduced results
+    size_t out_elems = 0;
+    hipfftHandle plan = nullptr;
+    bool has_plan = false;
+};
+
+void release_analysis(AnalysisCache* a) {
+    if (!a) return;
+    if (a->has_plan) (void)hipfftDestroy(a->plan);
+    if (a->u) (void)hipFree(a->u);
+    if (a->c) (void)hipFree(a->c);
+    if (a->part) (void)hipFree(a->part);
+    if (a->out) (void)hipFree(a->out);
+    delete a;
+}
+
+}  // namespace lbm
+
+namespace {
+
+AnalysisCache& cache(lbm_handle* h) {
+    if (!h->ana) h->ana = new AnalysisCache();
+    return *h->ana;
+}
+
+// Grow a cached device buffer to at least n elements of T.
+template <typename T>
+hipError_t ensure(T*& p, size_t& have, size_t n) {
+    if (p && have >= n) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    have = 0;
+    hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+    if (e == hipSuccess) have = n;
+    return e;
+}
+
+// Velocity (FP64, [3][ncell]) of the current state into the cached buffer.
+lbm_status velocity(lbm_handle* h, const double** u) {
+    AnalysisCache& a = cache(h);
     const size_t nc = h->args.ncell;
-    hipError_t e = hipMalloc(&u.p, 3 * nc * sizeof(double));
-    if (e != hipSuccess) return hip_err(h, e, "hipMalloc(velocity)");
-    e = launch_moments(h->cfg.precision, current_pattern(h), current_args(h), nullptr,
-                       (double*)u.p, h->stream);
+    if (!a.u) {
+        hipError_t e = hipMalloc((void**)&a.u, 3 * nc * sizeof(double));
+        if (e != hipSuccess) {
+            a.u = nullptr;
+            return hip_err(h, e, "hipMalloc(velocity)");
+        }
+    }
+    hipError_t e = launch_moments(h->cfg.precision, current_pattern(h), current_args(h), nullptr,
+                                  a.u, h->stream);
     if (e != hipSuccess) return hip_err(h, e, "moments kernel");
+    *u = a.u;
     return LBM_OK;
 }
 
@@ -161,33 +215,34 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
     const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
     const size_t nc = h->args.ncell, hx = nx / 2 + 1, nmodes = hx * (size_t)ny * nz;
-    DevBuf u, c, part, out;
-    lbm_status st = velocity(h, u);
+    const double* u = nullptr;
+    lbm_status st = velocity(h, &u);
     if (st != LBM_OK) return st;
-    hipError_t e = hipMalloc(&c.p, nmodes * sizeof(hipfftDoubleComplex));
-    if (e == hipSuccess) e = hipMalloc(&part.p, (size_t)kAnaBlocks * (kmax + 1) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&out.p, (size_t)(kmax + 1) * sizeof(double));
+    AnalysisCache& a = cache(h);
+    hipError_t e = ensure(a.c, a.c_elems, nmodes);
+    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
+    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(spectrum)");
-    hipfftHandle plan;
-    hipfftResult fr = hipfftPlan3d(&plan, (int)nz, (int)ny, (int)nx, HIPFFT_D2Z);
-    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
-    fr = hipfftSetStream(plan, h->stream);
+    if (!a.has_plan) {
+        hipfftResult fr = hipfftPlan3d(&a.plan, (int)nz, (int)ny, (int)nx, HIPFFT_D2Z);
+        if (fr != HIPFFT_SUCCESS)
+            return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
+        a.has_plan = true;
+    }
+    hipfftResult fr = hipfftSetStream(a.plan, h->stream);
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
-    for (int a = 0; a < 3 && fr == HIPFFT_SUCCESS; ++a) {
-        fr = hipfftExecD2Z(plan, (hipfftDoubleReal*)u.p + (size_t)a * nc, (hipfftDoubleComplex*)c.p);
+    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
+        fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
         if (fr != HIPFFT_SUCCESS) break;
         hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
-                           (const hipfftDoubleComplex*)c.p, nx, ny, nz, (int)kmax, inv_n2,
-                           (double*)part.p);
+                           (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
         hipLaunchKernelGGL(k_sum_rows, dim3((kmax + 1 + 255) / 256), dim3(256), 0, h->stream,
-                           (const double*)part.p, kAnaBlocks, (int)(kmax + 1), 1.0, a > 0,
-                           (double*)out.p);
+                           (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
     }
-    (void)hipfftDestroy(plan);
     if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(E, out.p, shm, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "spectrum");
     return LBM_OK;
@@ -201,8 +256,9 @@ lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr,
     if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
     const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
     const size_t nc = h->args.ncell;
-    DevBuf u, drs, part, res;
-    lbm_status st = velocity(h, u);
+    DevBuf drs, part, res;
+    const double* u = nullptr;
+    lbm_status st = velocity(h, &u);
     if (st != LBM_OK) return st;
     const int nb = (int)std::min<size_t>(kAnaBlocks, (nc + 255) / 256);
     hipError_t e = hipMalloc(&drs.p, nr * sizeof(int32_t));
@@ -211,7 +267,7 @@ lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr,
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(structure functions)");
     e = hipMemcpyAsync(drs.p, rs, nr * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return hip_err(h, e, "copy separations");
-    hipLaunchKernelGGL(k_structure, dim3(nb, nr), dim3(256), 0, h->stream, (const double*)u.p, nx,
+    hipLaunchKernelGGL(k_structure, dim3(nb, nr), dim3(256), 0, h->stream, u, nx,
                        ny, nz, (const int32_t*)drs.p, (double*)part.p);
     // rows of 6 sums per (r, block): reduce blocks in a fixed order per r
     for (int j = 0; j < nr; ++j)

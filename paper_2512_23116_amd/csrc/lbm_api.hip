@@ -612,6 +612,7 @@ void lbm_destroy(lbm_handle* h) {
     if (h->partials) (void)hipFree(h->partials);
     if (h->staging) (void)hipFree(h->staging);
     if (h->d_cells) (void)hipFree(h->d_cells);
+    lbm::release_analysis(h->ana);
     delete h;
 }
 

@@ -75,6 +75,11 @@ constexpr int kDiagSlots = 32;      // doubles per block partial
 
 }  // namespace lbm
 
+namespace lbm {
+struct AnalysisCache;                      // lbm_analysis.hip
+void release_analysis(AnalysisCache* a);   // NULL-safe
+}  // namespace lbm
+
 struct lbm_handle {
     lbm_config cfg;                          // copy; force_modes points into `modes`
     std::vector<lbm_force_mode> modes;
@@ -100,6 +105,9 @@ struct lbm_handle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    // FFT plan and velocity / transform buffers of the analysis calls, created
+    // on first use and kept until lbm_destroy
+    lbm::AnalysisCache* ana = nullptr;
     std::string err;
 };
 
