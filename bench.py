@@ -49,7 +49,11 @@ def counter_traffic(workload_key, family="k_step"):
     return None
 
 
-def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64, tb=0):
+def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64, tb=0,
+                maps=False):
+    """Time `steps` steps; every `diag_every` steps take the K_t statistics (and with
+    `maps` also the K_t field, keeping its mid-z slice on the host, and the energy
+    spectrum): the diagnostics of the workload run inside the timed region."""
     import torch
     stream = torch.cuda.Stream()
     cfg = params.forced_hit(N)
@@ -58,7 +62,12 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
                       temporal_block=tb, stream=stream)
     lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
     stats = [lat.stats()] if warmup == 0 else []
+    kt_slices, spectra = [], []
     lat.step(warmup)
+    if maps:
+        # one-time set-up outside the timed region: the FFT plan and the analysis buffers
+        lat.spectrum(N // 2)
+        lat.kt_field()
     lat.sync()
     events = []
     torch.cuda.synchronize()
@@ -75,6 +84,9 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
         done += n
         if diag_every and done % diag_every == 0:
             stats.append(lat.stats())
+            if maps:
+                kt_slices.append(lat.kt_field()[N // 2].copy())
+                spectra.append(lat.spectrum(N // 2))
     lat.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -97,6 +109,8 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
                         theta_mean=final["theta_mean"], n_snapshots=len(stats)),
                 kt_series=[dict(step=st["steps"], mean=st["kt_mean"], var=st["kt_var"],
                                 flat=st["kt_flat"]) for st in stats],
+                n_maps=len(kt_slices), n_spectra=len(spectra),
+                spectrum_last=[float(v) for v in spectra[-1][:26]] if spectra else None,
                 tau0=cfg["tau0"])
 
 
@@ -203,7 +217,7 @@ def main():
 
     log(f"main: {args.N}^3 {args.precision} {args.streaming}, {args.steps} steps")
     main_run = run_lattice(lbm, params, args.N, args.precision, args.streaming, args.steps,
-                           args.warmup, args.diag_every, args.steps_per_graph)
+                           args.warmup, args.diag_every, args.steps_per_graph, maps=True)
     log(f"main: {main_run['mlups']:.0f} MLUPS, {main_run['avg_launch_us']:.1f} us/launch, "
         f"{main_run['roofline']['frac']:.3f} of HBM peak")
     key = f"{args.N}_{args.precision}_{args.streaming}"
@@ -262,7 +276,9 @@ def main():
             "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C_s=0.1 "
                          f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
                          f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
-                         f"forcing, 1e-3 noise start, K_t stats every {args.diag_every} steps"),
+                         f"forcing, 1e-3 noise start; every {args.diag_every} steps K_t "
+                         "statistics, K_t map (mid-z slice to host) and energy spectrum, "
+                         "all inside the timed region"),
             "N": args.N, "precision": args.precision, "streaming": args.streaming,
             "steps_per_graph": args.steps_per_graph, "parallelism": "single GPU",
         },
@@ -273,6 +289,9 @@ def main():
                      "avg_launch_us": round(main_run["avg_launch_us"], 3)},
         "cpu_baseline": cpu,
         "kt": main_run["kt"],
+        "diagnostics": {"every": args.diag_every, "kt_stats": main_run["kt"]["n_snapshots"],
+                        "kt_maps": main_run["n_maps"], "spectra": main_run["n_spectra"],
+                        "spectrum_last_k0_25": main_run["spectrum_last"]},
     }
     if large:
         lr = large["roofline"]

@@ -49,14 +49,26 @@ __global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c,
         partials[(uint64_t)blockIdx.x * (kmax + 1) + k] = hist[k];
 }
 
-// out[j] (+)= sum over rows b of partials[b][j], fixed order, one thread per column.
+// out[g][j] (+)= scale * sum over rows b of partials[g][b][j], one block per
+// (column j, group g): thread t folds rows t, t + 256, ..., then a fixed tree
+// over the block, so the order of the sum is the same on every call.
 __global__ __launch_bounds__(256) void k_sum_rows(const double* partials, int rows, int cols,
                                                   double scale, int accumulate, double* out) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= cols) return;
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    const double* p = partials + (uint64_t)blockIdx.y * rows * cols;
     double s = 0.0;
-    for (int b = 0; b < rows; ++b) s += partials[(uint64_t)b * cols + j];
-    out[j] = accumulate ? out[j] + s * scale : s * scale;
+    for (int b = threadIdx.x; b < rows; b += 256) s += p[(uint64_t)b * cols + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = out + (uint64_t)blockIdx.y * cols + j;
+        *o = accumulate ? *o + red[0] * scale : red[0] * scale;
+    }
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -237,7 +249,7 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
         if (fr != HIPFFT_SUCCESS) break;
         hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
                            (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
-        hipLaunchKernelGGL(k_sum_rows, dim3((kmax + 1 + 255) / 256), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
                            (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
     }
     if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
@@ -269,11 +281,9 @@ lbm_status lbm_structure_functions(lbm_handle* h, const int32_t* rs, int32_t nr,
     if (e != hipSuccess) return hip_err(h, e, "copy separations");
     hipLaunchKernelGGL(k_structure, dim3(nb, nr), dim3(256), 0, h->stream, u, nx,
                        ny, nz, (const int32_t*)drs.p, (double*)part.p);
-    // rows of 6 sums per (r, block): reduce blocks in a fixed order per r
-    for (int j = 0; j < nr; ++j)
-        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, h->stream,
-                           (const double*)part.p + (size_t)j * nb * 6, nb, 6, 1.0 / (3.0 * nc), 0,
-                           (double*)res.p + (size_t)j * 6);
+    // rows of 6 sums per (r, block): reduce the blocks of each r in a fixed order
+    hipLaunchKernelGGL(k_sum_rows, dim3(6, nr), dim3(256), 0, h->stream, (const double*)part.p,
+                       nb, 6, 1.0 / (3.0 * nc), 0, (double*)res.p);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(out, res.p, (size_t)nr * 6 * sizeof(double),
                                             hipMemcpyDeviceToHost, h->stream);

@@ -111,28 +111,28 @@ __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
     }
 }
 
-// Reduce the per-block partials in a fixed order into result[0..kDiagUsed).
+// Reduce the per-block partials in a fixed order into result[0..kDiagUsed):
+// block j reduces slot j (thread t folds blocks t, t + 256, ..., then a fixed
+// tree over the 256 threads).
 __global__ __launch_bounds__(256) void k_diag_final(const double* partials, int nblocks,
                                                     double* result) {
     __shared__ double red[256];
-    for (int j = 0; j < kDiagUsed; ++j) {
-        double v = (j == 4) ? INFINITY : ((j == 5) ? -INFINITY : 0.0);
-        for (int b = threadIdx.x; b < nblocks; b += 256) {
-            const double x = partials[(uint64_t)b * kDiagSlots + j];
-            v = (j == 4) ? fmin(v, x) : ((j == 5) ? fmax(v, x) : v + x);
+    const int j = blockIdx.x;
+    double v = (j == 4) ? INFINITY : ((j == 5) ? -INFINITY : 0.0);
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        const double x = partials[(uint64_t)b * kDiagSlots + j];
+        v = (j == 4) ? fmin(v, x) : ((j == 5) ? fmax(v, x) : v + x);
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + s];
+            red[threadIdx.x] = (j == 4) ? fmin(a, b) : ((j == 5) ? fmax(a, b) : a + b);
         }
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                const double a = red[threadIdx.x], b = red[threadIdx.x + s];
-                red[threadIdx.x] = (j == 4) ? fmin(a, b) : ((j == 5) ? fmax(a, b) : a + b);
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) result[j] = red[0];
         __syncthreads();
     }
+    if (threadIdx.x == 0) result[j] = red[0];
 }
 
 // ------------------------------------------------------ observation ---
@@ -386,8 +386,8 @@ hipError_t launch_diag(int precision, int pat, const LatticeArgs& L, double* par
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, (const double*)partials, nblocks,
-                       result);
+    hipLaunchKernelGGL(k_diag_final, dim3(kDiagUsed), dim3(256), 0, s, (const double*)partials,
+                       nblocks, result);
     return hipGetLastError();
 }
 
