@@ -226,8 +226,16 @@ def lbm_kt_stats(h, allow_unstable=False):
     return st.as_dict()
 
 
-def lbm_kt_field(h, ncell):
-    kt = np.empty(ncell, dtype=np.float32)
+def lbm_kt_field(h, ncell, out=None):
+    """K_t per cell into `out` (C-contiguous float32 with ncell elements; a
+    page-locked buffer makes the copy one DMA) or into a new array."""
+    if out is None:
+        kt = np.empty(ncell, dtype=np.float32)
+    else:
+        if out.dtype != np.float32 or out.size != ncell or not out.flags.c_contiguous \
+                or not out.flags.writeable:
+            raise ValueError("out must be a writeable C-contiguous float32 array of ncell elements")
+        kt = out.reshape(-1)
     _check(lib().lbm_kt_field(h, kt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), h)
     return kt
 
@@ -396,8 +404,8 @@ class Lattice:
     def stats(self, allow_unstable=False):
         return lbm_kt_stats(self.handle, allow_unstable)
 
-    def kt_field(self):
-        return lbm_kt_field(self.handle, self.ncell).reshape(self.shape)
+    def kt_field(self, out=None):
+        return lbm_kt_field(self.handle, self.ncell, out).reshape(self.shape)
 
     def spectrum(self, kmax):
         return lbm_spectrum(self.handle, kmax)

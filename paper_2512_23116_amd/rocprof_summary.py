@@ -155,10 +155,27 @@ def main():
             acc[2] += 1
             acc[3] = fam
         if a.traffic_out:
-            with open(a.traffic_out, "a") as fh:
-                for key, (f, w, n, fam) in sorted(per_key.items()):
-                    fh.write(f"{key} {kernel_source_sha(fam)} {f / n:.6e} {w / n:.6e} "
-                             f"{fam} mean over {n} kernels\n")
+            write_traffic(a.traffic_out, per_key)
+
+
+def write_traffic(path, per_key):
+    """Rewrite the traffic table: its comment lines, the earlier entries that were
+    taken on the current sources of their kernel and not measured again now, then
+    the new entries.  Entries of older sources are dropped."""
+    current = {fam: kernel_source_sha(fam) for fam in KERNEL_SOURCES}
+    head, keep = [], []
+    if os.path.exists(path):
+        for ln in open(path):
+            if ln.startswith("#"):
+                head.append(ln)
+                continue
+            parts = ln.split()
+            if len(parts) >= 5 and parts[0] not in per_key and current.get(parts[4]) == parts[1]:
+                keep.append(ln)
+    with open(path, "w") as fh:
+        fh.writelines(head + keep)
+        for key, (f, w, n, fam) in sorted(per_key.items()):
+            fh.write(f"{key} {current[fam]} {f / n:.6e} {w / n:.6e} {fam} mean over {n} kernels\n")
 
 
 if __name__ == "__main__":

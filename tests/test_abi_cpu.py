@@ -142,3 +142,17 @@ def test_null_handles_are_rejected_without_touching_a_device(lbm):
         assert call() == lbm.LBM_ERR_INVALID_ARG
     assert L.lbm_steps_done(None) == -1 and L.lbm_num_cells(None) == -1
     L.lbm_destroy(None)
+
+
+def test_kt_field_out_buffer_is_checked_before_the_call(lbm):
+    """A caller-supplied K_t buffer of the wrong type, size or layout is refused on
+    the host, before the library is entered."""
+    import numpy as np
+    bad = [np.empty(8, np.float64), np.empty(7, np.float32),
+           np.empty((4, 4), np.float32)[:, :2]]
+    ro = np.empty(8, np.float32)
+    ro.flags.writeable = False
+    bad.append(ro)
+    for out in bad:
+        with pytest.raises(ValueError):
+            lbm.lbm_kt_field(None, 8, out)

@@ -229,6 +229,10 @@ def test_kt_stats_and_fields_match_oracle(lbm, orc, precision, tol):
     assert np.abs(u - u_o).max() <= tol * np.abs(u_o).max()
     kt = lat.kt_field()
     np.testing.assert_allclose(kt, np.float32(s3 * theta), rtol=max(tol, 2e-7), atol=0)
+    # into a caller-owned page-locked buffer: the same values
+    import torch
+    pinned = torch.empty(kt.size, dtype=torch.float32, pin_memory=True).numpy()
+    assert np.array_equal(lat.kt_field(out=pinned), kt)
 
 
 def test_stats_are_bitwise_reproducible_and_C0_is_dns(lbm):
