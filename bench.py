@@ -4,16 +4,19 @@
 Prints ONE JSON line.  The headline workload is forced-HIT LES on a 100^3
 periodic lattice in FP32 with in-place AA streaming (Re = 2e4 at U0 = 0.043,
 C_s = 0.1 in nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with seeded phases, 1e-3 noise start,
-on-device K_t statistics every 500 steps).  A "step" is one lattice time step:
-the fused stream-and-collide kernel over every cell.  ``value`` is MLUPS
+on-device K_t statistics, K_t map and energy spectrum every 500 steps).  A
+"step" is one lattice time step: the fused stream-and-collide kernel over
+every cell.  ``value`` is MLUPS
 (million lattice-cell updates per second) over the timed steps, with the
 state resident in HBM.
 
 Beside it the same line carries: the roofline of the step kernel (algorithmic
 bytes 2 * 19 * 4 per cell update over its average launch time, from HIP events
-on the kernel's stream), the 800^3 FP32 AA run, the batched-serving run
-(p50/p99 completion latency and aggregate MLUPS), and the FP64 C oracle timed
-on the host cores on a bounded sample.
+on the kernel's stream), the 800^3 FP32 runs (AA, A/B, A/B with two steps per
+pass), the 800^3 FP16 / BF16 storage runs with their K_t-statistics and
+spectral errors against the FP32 run, the batched-serving run (p50/p99
+completion latency and aggregate MLUPS), and the FP64 C oracle timed on the
+host cores on a bounded sample.
 """
 import argparse
 import json
@@ -50,10 +53,12 @@ def counter_traffic(workload_key, family="k_step"):
 
 
 def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64, tb=0,
-                maps=False):
+                maps=False, final_spectrum=0):
     """Time `steps` steps; every `diag_every` steps take the K_t statistics (and with
     `maps` also the K_t field, keeping its mid-z slice on the host, and the energy
-    spectrum): the diagnostics of the workload run inside the timed region."""
+    spectrum): the diagnostics of the workload run inside the timed region.  With
+    `final_spectrum` = K the spectrum E(0..K) of the last state is taken after the
+    clock stops."""
     import torch
     stream = torch.cuda.Stream()
     cfg = params.forced_hit(N)
@@ -95,6 +100,7 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
     wall = time.perf_counter() - t0
     kern_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
     final = lat.stats()
+    spec_final = lat.spectrum(final_spectrum) if final_spectrum else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -114,7 +120,7 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
                                 flat=st["kt_flat"]) for st in stats],
                 n_maps=len(kt_slices), n_spectra=len(spectra),
                 spectrum_last=[float(v) for v in spectra[-1][:26]] if spectra else None,
-                tau0=cfg["tau0"])
+                spectrum_final=spec_final, tau0=cfg["tau0"])
 
 
 def cpu_baseline(N, target_s=12.0):
@@ -135,6 +141,32 @@ def cpu_baseline(N, target_s=12.0):
     return dict(value=N ** 3 * n / dt / 1e6, unit="MLUPS", cores=ref_c.num_threads(),
                 kind="oracle",
                 sample=f"{N}^3 forced HIT, {n} steps of the plain C FP64 oracle (OpenMP)")
+
+
+def precision_errors(run, ref, N):
+    """Errors of a reduced-precision run against the FP32 run of the same workload:
+    relative error of the K_t mean / variance / flatness at every common snapshot
+    after step 0 (max over snapshots and at the last one; at step 0 the K_t
+    variance of the noise start is ~1e-21 and only measures the rounding of the
+    initial state) and the spectral error
+    max_{1<=k<=K} |E(k) / E_ref(k) - 1| of the last state for K = 8, 32, N/4."""
+    ref_by_step = {s["step"]: s for s in ref["kt_series"]}
+    worst = {"mean": 0.0, "var": 0.0, "flat": 0.0}
+    last = {}
+    for s in run["kt_series"]:
+        r = ref_by_step.get(s["step"])
+        if r is None or s["step"] == 0:
+            continue
+        for q in worst:
+            e = abs(s[q] - r[q]) / abs(r[q])
+            worst[q] = max(worst[q], e)
+            last[q] = e
+    spec = {}
+    if run["spectrum_final"] is not None and ref["spectrum_final"] is not None:
+        E, Er = run["spectrum_final"], ref["spectrum_final"]
+        for K in (8, 32, N // 4):
+            spec[f"k<={K}"] = max(abs(E[k] / Er[k] - 1.0) for k in range(1, K + 1))
+    return dict(kt_rel_err_max=worst, kt_rel_err_last=last, spectrum_rel_err_last=spec)
 
 
 def run_serving(n_req, steps, seed=2024):
@@ -170,12 +202,16 @@ def profile_run(lbm, params, args):
     del x, y
     torch.cuda.empty_cache()
     log("profile: 3 copies of 1 GiB done")
-    runs = [(args.N, args.streaming, 0, 8)]
+    p = args.precision
+    runs = [(args.N, p, args.streaming, 0, 8)]
     if not args.no_large:
-        runs += [(args.large_N, "aa", 0, 4), (args.large_N, "ab", 0, 4), (args.large_N, "ab", 2, 8)]
-    for N, streaming, tb, steps in runs:
-        run_lattice(lbm, params, N, args.precision, streaming, steps, 2, 0, spg=0, tb=tb)
-        log(f"profile: {N}^3 {args.precision} {streaming}{' two-step' if tb else ''}, "
+        runs += [(args.large_N, p, "aa", 0, 4), (args.large_N, p, "ab", 0, 4),
+                 (args.large_N, p, "ab", 2, 8)]
+        if not args.no_precision:
+            runs += [(args.large_N, "fp16", "aa", 0, 4), (args.large_N, "bf16", "aa", 0, 4)]
+    for N, prec, streaming, tb, steps in runs:
+        run_lattice(lbm, params, N, prec, streaming, steps, 2, 0, spg=0, tb=tb)
+        log(f"profile: {N}^3 {prec} {streaming}{' two-step' if tb else ''}, "
             f"{steps} steps of plain launches done")
 
 
@@ -196,6 +232,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-large-ab", action="store_true",
                     help="skip the 800^3 A/B (two-array) measurement beside the AA one")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 800^3 FP16 / BF16 storage runs compared with the FP32 one")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
@@ -232,7 +270,8 @@ def main():
         # no warm-up: K_t statistics from step 0 on (the module is loaded and the
         # clocks are up from the main run; graph capture costs ~1 ms of the timed span)
         large = run_lattice(lbm, params, args.large_N, "fp32", "aa", args.large_steps, 0,
-                            args.diag_every, args.steps_per_graph)
+                            args.diag_every, args.steps_per_graph,
+                            final_spectrum=0 if args.no_precision else args.large_N // 4)
         large["roofline"]["traffic"] = counter_traffic(f"{args.large_N}_fp32_aa")
         log(f"large: {large['mlups']:.0f} MLUPS, {large['roofline']['frac']:.3f} of HBM peak")
 
@@ -247,6 +286,26 @@ def main():
                                 args.diag_every, args.steps_per_graph, tb=2)
         log(f"large A/B two steps per pass: {large_tb2['mlups']:.0f} MLUPS, "
             f"{large_tb2['roofline']['frac']:.3f} of the single-step HBM roofline")
+
+    precision = {}
+    if large and not args.no_precision:
+        for prec in ("fp16", "bf16"):
+            log(f"precision: {args.large_N}^3 {prec} aa, {args.large_steps} steps")
+            pr = run_lattice(lbm, params, args.large_N, prec, "aa", args.large_steps, 0,
+                             args.diag_every, args.steps_per_graph,
+                             final_spectrum=args.large_N // 4)
+            rr = pr["roofline"]
+            precision[prec] = {
+                "workload": (f"forced HIT LES {args.large_N}^3, populations stored as {prec} "
+                             "deviations with a per-run scale, FP32 collision, FP64 reductions, AA"),
+                "mlups": round(pr["mlups"], 1), "steps": pr["steps"],
+                "ms_per_step": round(pr["ms_per_step"], 4),
+                "roofline": {"bound": "hbm", "achieved": round(rr["achieved"], 1),
+                             "peak": rr["peak"], "unit": "GB/s", "frac": round(rr["frac"], 4),
+                             "traffic": counter_traffic(f"{args.large_N}_{prec}_aa")},
+                "vs_fp32": precision_errors(pr, large, args.large_N)}
+            log(f"precision: {prec} {pr['mlups']:.0f} MLUPS, {rr['frac']:.3f} of HBM peak, "
+                f"K_t mean rel err {precision[prec]['vs_fp32']['kt_rel_err_max']['mean']:.2e}")
 
     serving = None
     if not args.no_serving:
@@ -333,6 +392,8 @@ def main():
                 "achieved": round(lr["achieved"], 1), "frac": round(lr["frac"], 4),
                 "note": "2*19*4 B per cell update / time: the bytes a one-step-per-pass "
                         "kernel must move for the same MLUPS"}}
+    if precision:
+        out["precision"] = precision
     if serving:
         out["serving"] = serving
     print(json.dumps(out), flush=True)

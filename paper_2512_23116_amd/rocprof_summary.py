@@ -47,13 +47,27 @@ def kernel_source_sha(family="k_step"):
     return h.hexdigest()[:16]
 
 
+CODEC_PRECISION = {"CdF64": "fp64", "CdF32": "fp32", "CdF16": "fp16", "CdBF16": "bf16"}
+PRECISION_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def kernel_precision(kernel, default):
+    """Storage precision named by a step kernel's codec template argument."""
+    for codec, p in CODEC_PRECISION.items():
+        if f"<{codec}," in short(kernel) or f"<{codec}>" in short(kernel):
+            return p
+    return default
+
+
 def lattice_key(kernel, grid, precision, tb2_n):
     """(family, traffic key) of a step-kernel launch, or None for other kernels.
 
     k_step launches one thread per cell (grid = N^3 rounded up to 256); the
-    pattern template argument tells AA (0, 1) from A/B (2).  The two-step kernel's
-    grid counts tiles, so its lattice edge is given (tb2_n)."""
+    pattern template argument tells AA (0, 1) from A/B (2), the codec argument
+    the storage precision (`precision` when it names none).  The two-step
+    kernel's grid counts tiles, so its lattice edge is given (tb2_n)."""
     k = short(kernel)
+    precision = kernel_precision(kernel, precision)
     if k.startswith("k_step_tb2"):
         return "k_step_tb2", f"{tb2_n}_{precision}_ab_tb2"
     if not k.startswith("k_step<"):
@@ -116,7 +130,6 @@ def main():
     ap.add_argument("--tb2-n", type=int, default=800,
                     help="lattice edge of the two-step kernel launches in the counter runs")
     a = ap.parse_args()
-    b = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[a.precision]
     if a.cmd:
         print(f"command: {a.cmd}")
     for fam in KERNEL_SOURCES:
@@ -146,7 +159,8 @@ def main():
             N = int(key.split("_")[0])
             f = statistics.mean(v) * 1024 * fcal
             w = statistics.mean(wb[(k, g)]) * 1024 * wcal
-            alg = 2 * 19 * b * N ** 3      # one read and one write of every population
+            kb = PRECISION_BYTES[key.split("_")[1]]
+            alg = 2 * 19 * kb * N ** 3     # one read and one write of every population
             print(f"{short(k)[:40]:40s} {key:>16s} {f / 1e9:9.4f} {w / 1e9:9.4f} {alg / 1e9:11.4f} "
                   f"{(f + w) / alg:6.3f}")
             acc = per_key[key]

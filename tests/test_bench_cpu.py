@@ -36,3 +36,24 @@ def test_traffic_table_travels_with_gpu_runs():
         pats = [l.strip() for l in open(ignore) if l.strip() and not l.startswith("#")]
         assert not any(p.rstrip("/") in ("profiles", "./profiles") or p.startswith("./profiles/")
                        or p.endswith(".txt") for p in pats), pats
+
+
+def test_precision_errors_compare_common_snapshots_after_the_start():
+    sys.path.insert(0, ROOT)
+    import bench
+    ref = {"kt_series": [dict(step=0, mean=1.0, var=1e-21, flat=3.0),
+                         dict(step=500, mean=2.0, var=4.0, flat=3.0),
+                         dict(step=1000, mean=2.0, var=4.0, flat=3.0)],
+           "spectrum_final": [0.0] + [1.0] * 40}
+    run = {"kt_series": [dict(step=0, mean=1.5, var=5e-21, flat=9.0),
+                         dict(step=500, mean=2.2, var=4.0, flat=3.0),
+                         dict(step=1000, mean=2.02, var=3.6, flat=3.3)],
+           "spectrum_final": [0.0] + [1.0] * 8 + [1.5] + [1.0] * 31}
+    e = bench.precision_errors(run, ref, 40)
+    assert abs(e["kt_rel_err_max"]["mean"] - 0.1) < 1e-12       # step 0 is left out
+    assert abs(e["kt_rel_err_last"]["mean"] - 0.01) < 1e-12
+    assert abs(e["kt_rel_err_max"]["var"] - 0.1) < 1e-12
+    assert abs(e["kt_rel_err_max"]["flat"] - 0.1) < 1e-12
+    assert e["spectrum_rel_err_last"]["k<=8"] == 0.0
+    assert abs(e["spectrum_rel_err_last"]["k<=32"] - 0.5) < 1e-12
+    assert set(e["spectrum_rel_err_last"]) == {"k<=8", "k<=32", "k<=10"}
