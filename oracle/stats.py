@@ -136,3 +136,55 @@ def isotropy(u):
     return dict(energy_frac=np.diag(R) / tr,
                 b=np.array([b[0, 0], b[1, 1], b[2, 2], b[0, 1], b[0, 2], b[1, 2]]),
                 II_b=II, III_b=III, lumley_xi=np.cbrt(III / 2.0), lumley_eta=np.sqrt(-II / 3.0))
+
+
+def one_dimensional_spectra(u):
+    """One-dimensional energy spectra of each velocity component along each axis
+    (App. spectral isotropy: the longitudinal and transverse spectra E_11, E_22).
+
+    E[c, a, k] = sum of |u_hat_c(q)|^2 over the wavevectors q with |q_a| = k,
+    u_hat = FFT(u) / ncells (integer wavenumbers, k = 0 .. max_a n_a // 2;
+    entries beyond n_a // 2 are zero).  Parseval per axis: sum_k E[c, a, k] =
+    <u_c^2>.  Axis a = 0, 1, 2 is x, y, z; u: (3, nz, ny, nx).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    _, nz, ny, nx = u.shape
+    n = nx * ny * nz
+    K = max(nx, ny, nz) // 2 + 1
+    out = np.zeros((3, 3, K))
+    array_axis = {0: 2, 1: 1, 2: 0}        # x varies along array axis 2, ...
+    for c in range(3):
+        uh = np.fft.fftn(u[c]) / n
+        p = uh.real ** 2 + uh.imag ** 2
+        for a in range(3):
+            ax = array_axis[a]
+            m = p.shape[ax]
+            line = p.sum(axis=tuple(d for d in range(3) if d != ax))
+            k = np.abs(np.fft.fftfreq(m, 1.0 / m)).round().astype(np.int64)
+            out[c, a] = np.bincount(k, weights=line, minlength=K)[:K]
+    return out
+
+
+def isotropy_coefficient(E):
+    """Spectral isotropy coefficient IC(k) from the one-dimensional spectra E[c, a, k]
+    of a cubic lattice (App. spectral isotropy).
+
+    Reading: in isotropic turbulence the transverse spectrum follows from the
+    longitudinal one, E_22 = (E_11 - k dE_11/dk) / 2 (Batchelor), so
+    IC(k) = (E_L - k dE_L/dk) / (2 E_T) equals 1; E_L is the mean of the three
+    longitudinal spectra E[a, a], E_T the mean of the six transverse ones
+    E[c, a], c != a.  The slope is the central difference in log-log space,
+    k dE_L/dk = E_L(k) (ln E_L(k+1) - ln E_L(k-1)) / (ln(k+1) - ln(k-1)), exact
+    for power laws.  Defined for 2 <= k <= K-2 with E_L(k +- 1) > 0 and
+    E_T(k) > 0, NaN elsewhere.
+    """
+    E = np.asarray(E, dtype=np.float64)
+    EL = (E[0, 0] + E[1, 1] + E[2, 2]) / 3.0
+    ET = (E[1, 0] + E[2, 0] + E[0, 1] + E[2, 1] + E[0, 2] + E[1, 2]) / 6.0
+    K = EL.size
+    ic = np.full(K, np.nan)
+    for k in range(2, K - 1):
+        if EL[k + 1] > 0.0 and EL[k - 1] > 0.0 and ET[k] > 0.0:
+            slope = (np.log(EL[k + 1]) - np.log(EL[k - 1])) / (np.log(k + 1.0) - np.log(k - 1.0))
+            ic[k] = (EL[k] - EL[k] * slope) / (2.0 * ET[k])
+    return ic
