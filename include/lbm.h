@@ -223,6 +223,25 @@ lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n
  * Synchronises. */
 lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
 
+/* One-dimensional energy spectra and the spectral isotropy coefficient of the
+ * current state (App. spectral isotropy: longitudinal and transverse spectra
+ * E_11, E_22 and IC(k)):
+ *   E[(3 c + a)(kmax + 1) + k] = sum of |u_hat_c(q)|^2 over the wavevectors q
+ *   with |q_a| = k,  u_hat = FFT(u) / ncells,
+ * for velocity component c and axis a (0, 1, 2 = x, y, z), integer k = 0..kmax
+ * (0 <= kmax <= 2048; zero beyond n_a / 2), so that sum_k E[c][a][k] = <u_c^2>.
+ * If ic is not NULL (cubic lattices only, else LBM_ERR_INVALID_ARG), ic[k] =
+ * (E_L - k dE_L/dk) / (2 E_T) at k = 2..kmax-1 (NaN elsewhere and where
+ * E_L(k +- 1) or E_T(k) is not positive): E_L, E_T are the means of the 3
+ * longitudinal (c = a) and 6 transverse spectra, k dE_L/dk = E_L times the
+ * central difference of ln E_L over ln k (exact for power laws).  The paper's printed
+ * ratio does not equal 1 for isotropic fields; this is the isotropic relation
+ * E_22 = (E_11 - k dE_11/dk) / 2, under which IC = 1.  FP64 FFT (hipFFT) on the
+ * device, sums with LDS atomics (last bits may vary between calls).  Host
+ * double[9 (kmax+1)] and double[kmax+1].  Shares the analysis buffers and FFT
+ * plan of lbm_spectrum.  Synchronises. */
+lbm_status lbm_spectra_1d(lbm_handle* h, int32_t kmax, double* E, double* ic);
+
 /* Longitudinal structure functions of the current state (Sec. 5.3): for each
  * separation rs[j] >= 1 (taken modulo the lattice size per axis),
  *   out[6 j + m] = mean over cells x and axes a of p_m(du),

@@ -49,6 +49,38 @@ __global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c,
         partials[(uint64_t)blockIdx.x * (kmax + 1) + k] = hist[k];
 }
 
+// Per-block partial sums of w |c|^2 / n^2 of one R2C output c[nz][ny][nx/2+1]
+// binned by |k_x|, |k_y| and |k_z| separately (0..kmax each):
+// partials[block][axis][k], axis 0, 1, 2 = x, y, z.  w = 2 for the kx > 0 modes
+// that stand for a conjugate pair (both members have the same |k_a|).
+__global__ __launch_bounds__(256) void k_axis_bin(const hipfftDoubleComplex* c, uint32_t nx,
+                                                  uint32_t ny, uint32_t nz, int kmax,
+                                                  double inv_n2, double* partials) {
+    extern __shared__ double hist[];
+    const int nb = 3 * (kmax + 1);
+    for (int k = threadIdx.x; k < nb; k += 256) hist[k] = 0.0;
+    __syncthreads();
+    const uint32_t hx = nx / 2 + 1;
+    const uint64_t total = (uint64_t)hx * ny * nz;
+    for (uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x; m < total;
+         m += (uint64_t)gridDim.x * 256) {
+        const uint32_t ix = (uint32_t)(m % hx);
+        const uint64_t r = m / hx;
+        const uint32_t iy = (uint32_t)(r % ny), iz = (uint32_t)(r / ny);
+        const int ax = (int)ix;
+        const int ay = (int)(iy <= ny / 2 ? iy : ny - iy);
+        const int az = (int)(iz <= nz / 2 ? iz : nz - iz);
+        const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
+        const hipfftDoubleComplex v = c[m];
+        const double p = w * (v.x * v.x + v.y * v.y) * inv_n2;
+        if (ax <= kmax) atomicAdd(&hist[ax], p);
+        if (ay <= kmax) atomicAdd(&hist[kmax + 1 + ay], p);
+        if (az <= kmax) atomicAdd(&hist[2 * (kmax + 1) + az], p);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += 256) partials[(uint64_t)blockIdx.x * nb + k] = hist[k];
+}
+
 // out[g][j] (+)= scale * sum over rows b of partials[g][b][j], one block per
 // (column j, group g): thread t folds rows t, t + 256, ..., then a fixed tree
 // over the block, so the order of the sum is the same on every call.
@@ -217,6 +249,21 @@ lbm_status velocity(lbm_handle* h, const double** u) {
     return LBM_OK;
 }
 
+// The handle's D2Z plan of its lattice (created on first use), bound to its stream.
+lbm_status fft_plan(lbm_handle* h, AnalysisCache& a) {
+    if (!a.has_plan) {
+        hipfftResult fr = hipfftPlan3d(&a.plan, (int)h->args.nz, (int)h->args.ny,
+                                       (int)h->args.nx, HIPFFT_D2Z);
+        if (fr != HIPFFT_SUCCESS)
+            return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
+        a.has_plan = true;
+    }
+    hipfftResult fr = hipfftSetStream(a.plan, h->stream);
+    if (fr != HIPFFT_SUCCESS)
+        return set_err(h, LBM_ERR_DEVICE, std::string("hipfftSetStream: ") + fft_error(fr));
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -235,13 +282,9 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
     if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(spectrum)");
-    if (!a.has_plan) {
-        hipfftResult fr = hipfftPlan3d(&a.plan, (int)nz, (int)ny, (int)nx, HIPFFT_D2Z);
-        if (fr != HIPFFT_SUCCESS)
-            return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
-        a.has_plan = true;
-    }
-    hipfftResult fr = hipfftSetStream(a.plan, h->stream);
+    st = fft_plan(h, a);
+    if (st != LBM_OK) return st;
+    hipfftResult fr = HIPFFT_SUCCESS;
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
     for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
@@ -257,6 +300,69 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (e == hipSuccess) e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "spectrum");
+    return LBM_OK;
+}
+
+lbm_status lbm_spectra_1d(lbm_handle* h, int32_t kmax, double* E, double* ic) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (!E || kmax < 0 || kmax > 2048) return set_err(h, LBM_ERR_INVALID_ARG, "kmax must be 0..2048");
+    if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
+    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
+    if (ic && (ny != nx || nz != nx))
+        return set_err(h, LBM_ERR_INVALID_ARG, "the isotropy coefficient needs a cubic lattice");
+    const size_t nc = h->args.ncell, nmodes = (nx / 2 + 1) * (size_t)ny * nz;
+    const int cols = 3 * (kmax + 1);
+    const double* u = nullptr;
+    lbm_status st = velocity(h, &u);
+    if (st != LBM_OK) return st;
+    AnalysisCache& a = cache(h);
+    hipError_t e = ensure(a.c, a.c_elems, nmodes);
+    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * cols);
+    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)3 * cols);
+    if (e != hipSuccess) return hip_err(h, e, "hipMalloc(one-dimensional spectra)");
+    st = fft_plan(h, a);
+    if (st != LBM_OK) return st;
+    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
+    hipfftResult fr = HIPFFT_SUCCESS;
+    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
+        fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
+        if (fr != HIPFFT_SUCCESS) break;
+        hipLaunchKernelGGL(k_axis_bin, dim3(kAnaBlocks), dim3(256), (size_t)cols * sizeof(double),
+                           h->stream, (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax,
+                           inv_n2, a.part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(cols), dim3(256), 0, h->stream, (const double*)a.part,
+                           kAnaBlocks, cols, 1.0, 0, a.out + (size_t)c * cols);
+    }
+    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(E, a.out, (size_t)3 * cols * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "one-dimensional spectra");
+    if (ic) {
+        // App. spectral isotropy, with the isotropic relation between the
+        // longitudinal and transverse spectra: IC = (E_L - k dE_L/dk) / (2 E_T),
+        // E_L / E_T the means of the 3 longitudinal / 6 transverse spectra, the
+        // slope k dE_L/dk = E_L dln E_L / dln k by a central difference in
+        // log-log space; NaN where it is undefined.
+        std::vector<double> EL(kmax + 1), ET(kmax + 1);
+        const size_t K = (size_t)kmax + 1;
+        for (size_t k = 0; k < K; ++k) {
+            // E[c][a][k] at E[(3 c + a) K + k]
+            EL[k] = (E[0 * K + k] + E[4 * K + k] + E[8 * K + k]) / 3.0;
+            ET[k] = (E[3 * K + k] + E[6 * K + k] + E[1 * K + k] + E[7 * K + k] + E[2 * K + k] +
+                     E[5 * K + k]) / 6.0;
+        }
+        for (size_t k = 0; k < K; ++k) {
+            ic[k] = NAN;
+            if (k >= 2 && k + 1 < K && EL[k + 1] > 0.0 && EL[k - 1] > 0.0 && ET[k] > 0.0) {
+                const double slope = (log(EL[k + 1]) - log(EL[k - 1])) /
+                                     (log((double)k + 1.0) - log((double)k - 1.0));
+                ic[k] = (EL[k] - EL[k] * slope) / (2.0 * ET[k]);
+            }
+        }
+    }
     return LBM_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = (
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
-    "lbm_spectrum", "lbm_structure_functions", "lbm_turbulence",
+    "lbm_spectrum", "lbm_spectra_1d", "lbm_structure_functions", "lbm_turbulence",
 )
 
 
@@ -142,6 +142,7 @@ def lib():
                                                   ctypes.c_int64, dp]),
         "lbm_synchronize": (ctypes.c_int, [H]),
         "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
+        "lbm_spectra_1d": (ctypes.c_int, [H, ctypes.c_int32, dp, dp]),
         "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
                                                    ctypes.c_int32, dp]),
         "lbm_turbulence": (ctypes.c_int, [H, ctypes.c_int32,
@@ -278,6 +279,14 @@ def lbm_spectrum(h, kmax):
     return E
 
 
+def lbm_spectra_1d(h, kmax, with_ic=True):
+    """(E[c, a, k] (3, 3, kmax+1), IC[k] or None)."""
+    E = np.empty((3, 3, kmax + 1))
+    ic = np.empty(kmax + 1) if with_ic else None
+    _check(lib().lbm_spectra_1d(h, kmax, _dp(E), _dp(ic) if with_ic else None), h)
+    return E, ic
+
+
 def lbm_structure_functions(h, rs):
     rs = np.ascontiguousarray(rs, dtype=np.int32)
     out = np.empty((len(rs), 6))
@@ -409,6 +418,9 @@ class Lattice:
 
     def spectrum(self, kmax):
         return lbm_spectrum(self.handle, kmax)
+
+    def spectra_1d(self, kmax, with_ic=True):
+        return lbm_spectra_1d(self.handle, kmax, with_ic)
 
     def structure_functions(self, rs):
         return lbm_structure_functions(self.handle, rs)

@@ -15,7 +15,9 @@ difference of E_k over the neighbouring snapshots.  Relative error:
 |eps - (<F.u> - dE_k/dt)| / eps, averaged over the window.  Isotropy (Sec. 3.3,
 Tab. isotropy_metrics): mean and standard deviation of the directional energy
 fractions E_i / E and the mean |b_ij| of the off-diagonal anisotropy over the
-window, from the Reynolds stresses lbm_turbulence returns.
+window, from the Reynolds stresses lbm_turbulence returns.  Spectral isotropy
+(App. spectral isotropy): the coefficient IC(k) of lbm_spectra_1d, averaged over
+the window, with its mean and largest departure from 1 over 2 <= k <= N/4.
 
     python -m paper_2512_23116_amd.studies.energy_balance [--N 128] [--t-end 400]
 """
@@ -49,10 +51,11 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         if step > lat.steps:
             lat.step(step - lat.steps)
         tb = lat.turbulence()
+        _, ic = lat.spectra_1d(N // 4 + 1)
         rows.append(dict(step=step, E=tb["energy"], P=tb["injection"],
                          eps_strain=tb["eps_strain"], eps_spec=tb["eps_spec"],
                          re_lambda=tb["re_lambda"], eta=tb["eta"],
-                         frac=tb["energy_frac"], b=tb["b"]))
+                         frac=tb["energy_frac"], b=tb["b"], ic=ic))
         if len(rows) % 50 == 0:
             log(f"energy balance {N}^3: t/t0 = {step / t0:g}, {time.time() - tic:.1f} s")
     lat.close()
@@ -64,7 +67,10 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         out.append(dict(t=r["step"] / t0, E=r["E"], P=r["P"], dEdt=dEdt,
                         err_strain=abs(r["eps_strain"] - bal) / r["eps_strain"],
                         err_spec=abs(r["eps_spec"] - bal) / r["eps_spec"],
-                        re_lambda=r["re_lambda"], eta=r["eta"], frac=r["frac"], b=r["b"]))
+                        re_lambda=r["re_lambda"], eta=r["eta"], frac=r["frac"], b=r["b"],
+                        ic=r["ic"]))
+    ic = np.mean([o["ic"] for o in out], axis=0)        # k = 0 .. N/4 + 1
+    band = ic[2:N // 4 + 1]
     summary = dict(
         N=N, Re=Re, tau0=tau0, F0=F0, window=[t_start, t_end], snapshots=len(out),
         mean_err_eps_strain=float(np.mean([o["err_strain"] for o in out])),
@@ -74,6 +80,8 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         energy_frac_mean=[float(v) for v in np.mean([o["frac"] for o in out], axis=0)],
         energy_frac_std=[float(v) for v in np.std([o["frac"] for o in out], axis=0)],
         mean_abs_b_offdiag=[float(v) for v in np.mean([np.abs(o["b"][3:]) for o in out], axis=0)],
+        ic_k2_to_kq=[float(v) for v in ic[2:N // 4 + 1]],
+        ic_band_mean=float(np.mean(band)), ic_band_max_dev=float(np.max(np.abs(band - 1.0))),
         paper_err={128: "6-7 %", 256: "< 3.5 %", 512: "~1 % (Re 5000)"}.get(N),
         wall_s=time.time() - tic)
     return summary, out

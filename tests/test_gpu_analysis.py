@@ -82,3 +82,41 @@ def test_turbulence_scales_match_oracle(lbm, N, precision, tau_mode, rtol):
     with pytest.raises(lbm.LbmError):
         odd.turbulence()
     odd.close()
+
+
+@pytest.mark.parametrize("shape,precision,rtol", [((32, 32, 32), "fp64", 1e-10),
+                                                  ((17, 9, 30), "fp64", 1e-10),
+                                                  ((100, 100, 100), "fp32", 1e-10)])
+def test_one_dimensional_spectra_and_isotropy_coefficient_match_oracle(lbm, shape, precision,
+                                                                       rtol):
+    """lbm_spectra_1d against the oracle's definitions applied to the GPU's own
+    velocity field (App. spectral isotropy)."""
+    lat = lbm.Lattice(shape, 0.52, 0.13, forced_modes(F0=3e-5, seed=4), precision=precision,
+                      smag_form=1)
+    lat.init(lbm.LBM_INIT_NOISE, 0.02, 23)
+    lat.step(30)
+    _, u = lat.moments()
+    kmax = max(shape) // 2 + 2
+    cubic = len(set(shape)) == 1
+    E, ic = lat.spectra_1d(kmax, with_ic=cubic)
+    ref = ST.one_dimensional_spectra(u)
+    E_ref = np.zeros((3, 3, kmax + 1))
+    m = min(kmax + 1, ref.shape[2])
+    E_ref[:, :, :m] = ref[:, :, :m]
+    np.testing.assert_allclose(E, E_ref, rtol=rtol, atol=1e-14 * E_ref.max())
+    for c in range(3):
+        for a in range(3):
+            assert abs(E[c, a].sum() - (u[c] ** 2).mean()) <= 1e-10 * (u[c] ** 2).mean()
+    if cubic:
+        ic_ref = ST.isotropy_coefficient(E_ref)
+        assert np.array_equal(np.isnan(ic), np.isnan(ic_ref))
+        ok = ~np.isnan(ic_ref)
+        np.testing.assert_allclose(ic[ok], ic_ref[ok], rtol=1e-9, atol=1e-12)
+        print(f"{shape} {precision}: IC(2..9) = {np.round(ic[2:10], 3)}", flush=True)
+    else:
+        with pytest.raises(lbm.LbmError):
+            lat.spectra_1d(kmax, with_ic=True)
+        lat.spectra_1d(kmax, with_ic=False)           # still usable after the error
+    with pytest.raises(lbm.LbmError):
+        lat.spectra_1d(2049, with_ic=False)
+    lat.close()

@@ -38,6 +38,8 @@ def test_energy_balance_study_small():
     for r in rows:
         assert r["E"] > 0 and r["P"] > 0 and math.isfinite(r["dEdt"])
     assert summary["mean_err_eps_strain"] < 0.2, summary
+    assert len(summary["ic_k2_to_kq"]) == 11
+    assert all(math.isfinite(v) and v > 0 for v in summary["ic_k2_to_kq"]), summary
 
 
 def test_intermittency_study_small():
