@@ -18,6 +18,9 @@ fractions E_i / E and the mean |b_ij| of the off-diagonal anisotropy over the
 window, from the Reynolds stresses lbm_turbulence returns.  Spectral isotropy
 (App. spectral isotropy): the coefficient IC(k) of lbm_spectra_1d, averaged over
 the window, with its mean and largest departure from 1 over 2 <= k <= N/4.
+Spectrum (Sec. 3.4, Fig. DNS_spectra_validation): the window-averaged shell
+spectrum in Kolmogorov units (eps = <F.u>, nu = nu0) against Pope's model
+spectrum carrying the same energy and dissipation (studies/pope.py).
 
     python -m paper_2512_23116_amd.studies.energy_balance [--N 128] [--t-end 400]
 """
@@ -47,11 +50,13 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
     log(f"energy balance {N}^3 Re {Re:g}: reached t/t0 = {t_start - every / t0:g} "
         f"in {time.time() - tic:.1f} s")
     rows = []
+    spec = np.zeros(N // 2 + 1)
     for step in range(t_start * t0 - every, t_end * t0 + every + 1, every):
         if step > lat.steps:
             lat.step(step - lat.steps)
         tb = lat.turbulence()
         _, ic = lat.spectra_1d(N // 4 + 1)
+        spec += lat.spectrum(N // 2)
         rows.append(dict(step=step, E=tb["energy"], P=tb["injection"],
                          eps_strain=tb["eps_strain"], eps_spec=tb["eps_spec"],
                          re_lambda=tb["re_lambda"], eta=tb["eta"],
@@ -59,6 +64,7 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         if len(rows) % 50 == 0:
             log(f"energy balance {N}^3: t/t0 = {step / t0:g}, {time.time() - tic:.1f} s")
     lat.close()
+    spec /= len(rows)
     out = []
     for i in range(1, len(rows) - 1):
         dEdt = (rows[i + 1]["E"] - rows[i - 1]["E"]) / (rows[i + 1]["step"] - rows[i - 1]["step"])
@@ -71,6 +77,13 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
                         ic=r["ic"]))
     ic = np.mean([o["ic"] for o in out], axis=0)        # k = 0 .. N/4 + 1
     band = ic[2:N // 4 + 1]
+    from . import pope
+    nu0 = (tau0 - 0.5) / 3.0
+    eps = float(np.mean([r["P"] for r in rows]))
+    eta = (nu0 ** 3 / eps) ** 0.25
+    k_eta = 2 * np.pi * np.arange(1, N // 2 + 1) / N * eta
+    E_kol = spec[1:] * N / (2 * np.pi) / (eps * nu0 ** 5) ** 0.25
+    pm = pope.compare(k_eta, E_kol)
     summary = dict(
         N=N, Re=Re, tau0=tau0, F0=F0, window=[t_start, t_end], snapshots=len(out),
         mean_err_eps_strain=float(np.mean([o["err_strain"] for o in out])),
@@ -82,6 +95,8 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         mean_abs_b_offdiag=[float(v) for v in np.mean([np.abs(o["b"][3:]) for o in out], axis=0)],
         ic_k2_to_kq=[float(v) for v in ic[2:N // 4 + 1]],
         ic_band_mean=float(np.mean(band)), ic_band_max_dev=float(np.max(np.abs(band - 1.0))),
+        k_eta=[float(v) for v in k_eta], E_kolmogorov=[float(v) for v in E_kol],
+        pope={k: v for k, v in pm.items()},
         paper_err={128: "6-7 %", 256: "< 3.5 %", 512: "~1 % (Re 5000)"}.get(N),
         wall_s=time.time() - tic)
     return summary, out

@@ -14,7 +14,8 @@ functions; the study reports the time-averaged spectrum in Kolmogorov units
 shell energy divided by the shell width 2 pi / N, nu the molecular
 viscosity and eps the injected power <F.u>, which equals the total dissipation
 in the steady window), the flatness F4(r)
-against r / eta, the ESS exponents, and for the LES the statistics of
+against r / eta, the ESS exponents, for the DNS the comparison with Pope's model
+spectrum (studies/pope.py, Sec. 3.4), and for the LES the statistics of
 theta = tau_e - 1/2 (Sec. 5.1).
 
     python -m paper_2512_23116_amd.studies.iso_re_pair [--scale 2] [--t-end 300]
@@ -93,6 +94,9 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log):
     x = np.log(S[sel, 2])
     out["zeta"] = {p: float(np.polyfit(x, np.log(S[sel, c]), 1)[0]) for p, c in ORDERS.items()}
     out["r_fit"] = [lo, hi]
+    if C == 0:
+        from . import pope
+        out["pope"] = pope.compare(out["k_eta"], out["E_kolmogorov"])
     if th:
         a = np.array(th)
         out["theta_mean"] = float(a[:, 0].mean())

@@ -40,6 +40,13 @@ def test_energy_balance_study_small():
     assert summary["mean_err_eps_strain"] < 0.2, summary
     assert len(summary["ic_k2_to_kq"]) == 11
     assert all(math.isfinite(v) and v > 0 for v in summary["ic_k2_to_kq"]), summary
+    pm = summary["pope"]
+    assert len(summary["E_kolmogorov"]) == 24
+    if pm["converged"]:
+        assert pm["c_L"] > 0 and pm["c_eta"] > 0 and math.isfinite(pm["mean_abs_log_ratio"])
+        assert len(pm["E_model"]) == 24
+    print("48^3 short DNS vs Pope's model:", {k: v for k, v in pm.items() if k != "E_model"},
+          flush=True)
 
 
 def test_intermittency_study_small():
