@@ -187,7 +187,8 @@ def run_serving(n_req, steps, seed=2024):
     return dict(requests=n_req, steps_each=steps, arrival_rate_per_s=rate,
                 p50_s=res["p50_s"], p99_s=res["p99_s"], aggregate_mlups=res["aggregate_mlups"],
                 busy_mlups=res["busy_mlups"], busy_frac=res["busy_frac"], failed=res["failed"],
-                capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80)
+                capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80,
+                group_mb=serving.GROUP_BYTES >> 20)
 
 
 def profile_run(lbm, params, args):

@@ -67,3 +67,24 @@ def test_request_stream_is_seeded():
     assert all(0.08 <= r.C <= 0.18 and 0.505 <= r.tau0 <= 0.55 for r in a)
     arr = [r.arrival for r in a]
     assert arr == sorted(arr) and arr[-1] == pytest.approx(32.0, rel=0.5)
+
+
+def test_cache_groups_pack_states_first_fit_decreasing():
+    from paper_2512_23116_amd.serving import Request, cache_groups
+    mb = 1 << 20
+    reqs = [Request(rid=i, N=n, C=0.1, tau0=0.51, force_seed=i, init_seed=i, arrival=0.0)
+            for i, n in enumerate([32, 128, 96, 64, 128, 48, 96])]
+    steps = [64, 64, 8, 64, 64, 64, 64]
+    groups = cache_groups(reqs, steps, 192 * mb)
+    # every pair appears once, with its steps
+    flat = sorted((r.rid, s) for g in groups for r, s in g)
+    assert flat == sorted((r.rid, s) for r, s in zip(reqs, steps))
+    for g in groups:
+        assert sum(r.state_bytes for r, _ in g) <= 192 * mb
+    # largest first: 128^3 (152 MiB) + 64^3 + 48^3 + 32^3, then the other 128^3,
+    # then the two 96^3
+    assert [[r.N for r, _ in g] for g in groups] == [[128, 64, 48, 32], [128], [96, 96]]
+    # no limit: one group in the given order; a state above the limit stands alone
+    assert cache_groups(reqs, steps, None) == [list(zip(reqs, steps))]
+    assert [len(g) for g in cache_groups(reqs[1:2], steps[1:2], 64 * mb)] == [1]
+    assert cache_groups([], [], 192 * mb) == []
