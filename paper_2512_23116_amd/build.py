@@ -37,5 +37,24 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+EXAMPLE_SRC = os.path.join(HERE, "examples", "forced_hit.c")
+EXAMPLE = os.path.join(HERE, "examples", "forced_hit")
+
+
+def build_examples(verbose=False):
+    """Plain-C example linked against the in-tree liblbm.so (found next to the
+    package at run time through an $ORIGIN-relative rpath)."""
+    cc = os.environ.get("CC", "gcc")
+    cmd = [cc, "-O2", "-std=c11", "-Wall", "-Wextra", "-I", os.path.join(ROOT, "include"),
+           EXAMPLE_SRC, "-L" + HERE, "-llbm", "-Wl,-rpath,$ORIGIN/..",
+           "-Wl,-rpath-link,/opt/rocm/lib", "-o", EXAMPLE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    return EXAMPLE
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])
+    build_examples(verbose=True)
