@@ -29,15 +29,6 @@ def test_counter_traffic_is_keyed_by_kernel_sources():
     assert bench.counter_traffic("no_such_lattice") is None
 
 
-def test_traffic_table_travels_with_gpu_runs():
-    """bench.py reads profiles/hbm_traffic.txt at run time, so GPU snapshots keep it."""
-    ignore = os.path.join(ROOT, ".gpurunignore")
-    if os.path.exists(ignore):
-        pats = [l.strip() for l in open(ignore) if l.strip() and not l.startswith("#")]
-        assert not any(p.rstrip("/") in ("profiles", "./profiles") or p.startswith("./profiles/")
-                       or p.endswith(".txt") for p in pats), pats
-
-
 def test_precision_errors_compare_common_snapshots_after_the_start():
     sys.path.insert(0, ROOT)
     import bench
