@@ -211,6 +211,20 @@ lbm_status lbm_set_populations(lbm_handle* h, const double* f);
  * cells[i] (0 <= cells[i] < ncells).  Host arrays.  Synchronises. */
 lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n, double* out);
 
+/* Fixed-bin histogram of theta = tau_e - 1/2 over the cells of the current
+ * state (Sec. 5.1 shows its distribution; eq. les_viscosity), theta per cell as
+ * in lbm_kt_field (FP64 from the kernel's tau_t):
+ *   counts[0]          cells with theta < lo,
+ *   counts[1 + b]      cells with floor((theta - lo) * (nbins / (hi - lo))) = b,
+ *                      b = 0..nbins-1 (the product taken in FP64),
+ *   counts[nbins + 1]  cells whose bin index would be >= nbins,
+ *   counts[nbins + 2]  cells with a non-finite theta.
+ * Host int64[nbins + 3]; exact integer counts (they sum to the cell count).
+ * 1 <= nbins <= 4096, lo < hi finite.  Uses a device buffer the handle keeps
+ * until lbm_destroy.  Synchronises. */
+lbm_status lbm_theta_histogram(lbm_handle* h, double lo, double hi, int32_t nbins,
+                               int64_t* counts);
+
 /* Shell-binned kinetic-energy spectrum of the current state (Sec. 2.2,
  * eq. integral_length_scale with the squared modulus):
  *   E[k] = 1/2 sum_{k - 1/2 <= |q| < k + 1/2} |u_hat(q)|^2,  u_hat = FFT(u) / ncells,

@@ -189,6 +189,8 @@ lbm_status hip_err(lbm_handle* h, hipError_t e, const char* what) {
 namespace lbm {
 
 struct AnalysisCache {
+    unsigned long long* hist = nullptr;   // theta histogram counts
+    size_t hist_elems = 0;
     double* u = nullptr;                  // [3][ncell] velocity, FP64
     hipfftDoubleComplex* c = nullptr;     // [nz][ny][nx/2+1] transform of one component
     size_t c_elems = 0;
@@ -203,6 +205,7 @@ struct AnalysisCache {
 void release_analysis(AnalysisCache* a) {
     if (!a) return;
     if (a->has_plan) (void)hipfftDestroy(a->plan);
+    if (a->hist) (void)hipFree(a->hist);
     if (a->u) (void)hipFree(a->u);
     if (a->c) (void)hipFree(a->c);
     if (a->part) (void)hipFree(a->part);
@@ -300,6 +303,28 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (e == hipSuccess) e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "spectrum");
+    return LBM_OK;
+}
+
+lbm_status lbm_theta_histogram(lbm_handle* h, double lo, double hi, int32_t nbins,
+                               int64_t* counts) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (!counts || nbins < 1 || nbins > 4096)
+        return set_err(h, LBM_ERR_INVALID_ARG, "nbins must be 1..4096 and counts non-NULL");
+    if (!(std::isfinite(lo) && std::isfinite(hi) && hi > lo))
+        return set_err(h, LBM_ERR_INVALID_ARG, "need finite lo < hi");
+    if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
+    AnalysisCache& a = cache(h);
+    const size_t n = (size_t)nbins + 3;
+    hipError_t e = ensure(a.hist, a.hist_elems, n);
+    if (e == hipSuccess) e = hipMemsetAsync(a.hist, 0, n * sizeof(unsigned long long), h->stream);
+    if (e == hipSuccess)
+        e = launch_theta_hist(h->cfg.precision, current_pattern(h), current_args(h), lo,
+                              (double)nbins / (hi - lo), (int)nbins, a.hist, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts, a.hist, n * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "theta histogram");
     return LBM_OK;
 }
 

@@ -157,12 +157,12 @@ __global__ __launch_bounds__(256) void k_moments(LatticeArgs L, double* rho, dou
     }
 }
 
+// theta = tau_e - 1/2 of one cell of the current state (eq. les_viscosity), in
+// FP64 from the kernel's own tau_t: the value behind the K_t field and the
+// theta histogram.
 template <class Cd, int PAT>
-__global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
-    using T = typename Cd::T;
+__device__ __forceinline__ double cell_theta(const LatticeArgs& L, uint32_t cell) {
     using R = typename Cd::R;
-    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
-    if (cell >= L.ncell) return;
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
     R g[19];
@@ -170,8 +170,44 @@ __global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
     const CellMacro<R> m = collide<R, false>(g, Fx, Fy, Fz, collide_const<R>(L));
-    const double theta = (L.tau0 - 0.5) + (double)m.tau_t;
+    return (L.tau0 - 0.5) + (double)m.tau_t;
+}
+
+template <class Cd, int PAT>
+__global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= L.ncell) return;
+    const double theta = cell_theta<Cd, PAT>(L, cell);
     kt[cell] = (float)(1.7320508075688772 * theta);   // K_t = sqrt(3) theta, ell = delta_x
+}
+
+// Fixed-bin histogram of theta: counts[0] below lo, counts[1 + b] for
+// b = floor((theta - lo) * inv_w) in 0..nbins-1, counts[nbins + 1] at or above
+// the top edge, counts[nbins + 2] non-finite.  Per-block LDS counts, then one
+// 64-bit integer atomic per non-empty bin: the totals are exact.
+template <class Cd, int PAT>
+__global__ __launch_bounds__(256) void k_theta_hist(LatticeArgs L, double lo, double inv_w,
+                                                    int nbins, unsigned long long* counts) {
+    extern __shared__ unsigned int hist[];
+    for (int k = threadIdx.x; k < nbins + 3; k += 256) hist[k] = 0u;
+    __syncthreads();
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell < L.ncell) {
+        const double theta = cell_theta<Cd, PAT>(L, cell);
+        int b;
+        if (!isfinite(theta)) {
+            b = nbins + 2;
+        } else if (theta < lo) {
+            b = 0;
+        } else {
+            const double q = floor((theta - lo) * inv_w);
+            b = q >= (double)nbins ? nbins + 1 : 1 + (int)q;
+        }
+        atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbins + 3; k += 256)
+        if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
 }
 
 // Slot and cell of f_i(x) for a runtime direction.
@@ -406,6 +442,18 @@ hipError_t launch_ktfield(int precision, int pat, const LatticeArgs& L, float* k
         using Cd = decltype(cd);
         constexpr int P = decltype(pt)::value;
         hipLaunchKernelGGL((k_ktfield<Cd, P>), grid_for(L.ncell), dim3(256), 0, s, L, kt);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_theta_hist(int precision, int pat, const LatticeArgs& L, double lo, double inv_w,
+                             int nbins, unsigned long long* counts, hipStream_t s) {
+    return dispatch(precision, pat, [&](auto cd, auto pt) {
+        using Cd = decltype(cd);
+        constexpr int P = decltype(pt)::value;
+        hipLaunchKernelGGL((k_theta_hist<Cd, P>), grid_for(L.ncell), dim3(256),
+                           (size_t)(nbins + 3) * sizeof(unsigned int), s, L, lo, inv_w, nbins,
+                           counts);
         return hipGetLastError();
     });
 }

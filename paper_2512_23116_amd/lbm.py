@@ -34,7 +34,8 @@ EXPORTS = (
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
-    "lbm_spectrum", "lbm_spectra_1d", "lbm_structure_functions", "lbm_turbulence",
+    "lbm_theta_histogram", "lbm_spectrum", "lbm_spectra_1d", "lbm_structure_functions",
+    "lbm_turbulence",
 )
 
 
@@ -141,6 +142,8 @@ def lib():
         "lbm_sample_populations": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int64),
                                                   ctypes.c_int64, dp]),
         "lbm_synchronize": (ctypes.c_int, [H]),
+        "lbm_theta_histogram": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
         "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
         "lbm_spectra_1d": (ctypes.c_int, [H, ctypes.c_int32, dp, dp]),
         "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
@@ -271,6 +274,13 @@ def lbm_save_state(h):
 def lbm_load_state(h, buf, steps):
     buf = np.ascontiguousarray(buf, dtype=np.uint8)
     _check(lib().lbm_load_state(h, buf.ctypes.data, buf.size, steps), h)
+
+
+def lbm_theta_histogram(h, lo, hi, nbins):
+    counts = np.empty(nbins + 3, dtype=np.int64)
+    _check(lib().lbm_theta_histogram(h, lo, hi, nbins,
+                                     counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), h)
+    return counts
 
 
 def lbm_spectrum(h, kmax):
@@ -415,6 +425,9 @@ class Lattice:
 
     def kt_field(self, out=None):
         return lbm_kt_field(self.handle, self.ncell, out).reshape(self.shape)
+
+    def theta_histogram(self, lo, hi, nbins):
+        return lbm_theta_histogram(self.handle, lo, hi, nbins)
 
     def spectrum(self, kmax):
         return lbm_spectrum(self.handle, kmax)

@@ -11,8 +11,12 @@ percentile below about 1.82e-3, the 5th above 1.0e-3 and no negative values
     python -m paper_2512_23116_amd.studies.regime [--smag-form 0|1] [--t-end 600]
 
 Per snapshot the K_t field comes back from the device (lbm_kt_field) and the
-host takes the domain mean and percentiles of theta = K_t / sqrt(3); the run
-prints one JSON line with the window averages.
+host takes the domain mean and percentiles of theta = K_t / sqrt(3); beside it
+the device histogram of theta (lbm_theta_histogram, `hist_bins` fixed bins on
+[0, hist_hi)) is accumulated over the window, giving the distribution of theta
+and percentiles read from it without moving the field (what a lattice too large
+to copy per snapshot would use).  The run prints one JSON line with the window
+averages.
 """
 import argparse
 import json
@@ -23,8 +27,29 @@ import time
 import numpy as np
 
 
+def histogram_percentiles(counts, lo, hi, ps):
+    """Percentiles of theta from fixed-bin counts [under, bins..., over, nonfinite],
+    linear within the bin that holds each one (under / over bins clamp to lo / hi)."""
+    nb = len(counts) - 3
+    c = np.asarray(counts[:nb + 2], dtype=np.float64)
+    cum = np.cumsum(c)
+    edges = np.concatenate([[lo], lo + (hi - lo) * np.arange(1, nb + 1) / nb, [hi]])
+    out = []
+    for p in ps:
+        target = p / 100.0 * cum[-1]
+        k = int(np.searchsorted(cum, target, side="left"))
+        if k == 0:
+            out.append(float(lo))
+        elif k >= nb + 1:
+            out.append(float(hi))
+        else:                                   # inside bin k - 1: [edges[k-1], edges[k])
+            frac = (target - cum[k - 1]) / c[k] if c[k] > 0 else 0.0
+            out.append(float(edges[k - 1] + frac * (edges[k] - edges[k - 1])))
+    return out
+
+
 def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None,
-        log=lambda m: print(m, file=sys.stderr, flush=True)):
+        hist_bins=400, hist_hi=4e-3, log=lambda m: print(m, file=sys.stderr, flush=True)):
     import torch
     from .. import lbm, params
     from ..inputs import paper_modes
@@ -37,6 +62,7 @@ def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None
     lat.init(lbm.LBM_INIT_TGV3D, U0 if amp is None else amp)
     t0 = 1000
     rows = []
+    hist = np.zeros(hist_bins + 3, dtype=np.int64)
     tic = time.time()
     lat.step(t_start * t0)
     lat.sync()
@@ -45,6 +71,7 @@ def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None
         if step > lat.steps:
             lat.step(step - lat.steps)
         th = lat.kt_field().astype(np.float64) / math.sqrt(3.0)
+        hist += lat.theta_histogram(0.0, hist_hi, hist_bins)
         sl = th[N // 2]                         # slice k = 50 (z index)
         st = lat.stats()
         rows.append(dict(t=step / t0, mean=float(th.mean()), p5=float(np.percentile(th, 5)),
@@ -58,10 +85,14 @@ def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None
     win["max"] = float(max(r["max"] for r in rows))
     win["min"] = float(min(r["min"] for r in rows))
     theta0 = tau0 - 0.5
+    hp = histogram_percentiles(hist, 0.0, hist_hi, (5, 50, 95, 99))
     return dict(setup=dict(N=N, tau0=tau0, C=C, smag_form=smag_form, F0=F0, U0=U0,
                            window=[t_start, t_end], snapshots=len(rows), every=every),
                 window_mean=win, normalised_mean=win["mean"] / theta0,
                 normalised_p95=win["p95"] / theta0,
+                histogram=dict(lo=0.0, hi=hist_hi, bins=hist_bins,
+                               counts=[int(v) for v in hist],
+                               pooled_percentiles=dict(zip(("p5", "p50", "p95", "p99"), hp))),
                 paper=dict(mean=1.34e-3, p95_below=1.82e-3, p5_above=1.0e-3, normalised_mean=2.08),
                 wall_s=time.time() - tic)
 

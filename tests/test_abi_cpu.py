@@ -134,6 +134,9 @@ def test_null_handles_are_rejected_without_touching_a_device(lbm):
         lambda: L.lbm_get_populations(None, dp),
         lambda: L.lbm_set_populations(None, dp),
         lambda: L.lbm_spectrum(None, 4, dp),
+        lambda: L.lbm_theta_histogram(None, 0.0, 1.0, 4,
+                                      np.zeros(8, np.int64).ctypes.data_as(
+                                          ctypes.POINTER(ctypes.c_int64))),
         lambda: L.lbm_spectra_1d(None, 4, dp, dp),
         lambda: L.lbm_structure_functions(None, rs, 1, dp),
         lambda: L.lbm_turbulence(None, 0, ctypes.byref(ts)),

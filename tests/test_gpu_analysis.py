@@ -148,3 +148,57 @@ def test_analysis_on_tiny_lattices(lbm, shape):
         want[:, :, :m] = r1[:, :, :m]
         np.testing.assert_allclose(E1, want, rtol=1e-10, atol=1e-18)
     lat.close()
+
+
+def _bin_counts(theta, lo, hi, nbins):
+    """The histogram rule of lbm_theta_histogram applied on the host in FP64."""
+    inv_w = nbins / (hi - lo)
+    counts = np.zeros(nbins + 3, dtype=np.int64)
+    fin = np.isfinite(theta)
+    counts[nbins + 2] = (~fin).sum()
+    t = theta[fin]
+    below = t < lo
+    counts[0] = below.sum()
+    q = np.floor((t[~below] - lo) * inv_w)
+    over = q >= nbins
+    counts[nbins + 1] = over.sum()
+    counts[1:nbins + 1] = np.bincount(q[~over].astype(np.int64), minlength=nbins)[:nbins]
+    return counts
+
+
+@pytest.mark.parametrize("shape,precision,streaming", [((32, 32, 32), "fp64", "aa"),
+                                                       ((30, 26, 34), "fp32", "ab"),
+                                                       ((30, 26, 34), "fp32", "aa")])
+def test_theta_histogram_matches_oracle(lbm, shape, precision, streaming):
+    """Counts of the device histogram against the oracle's theta of the GPU's own
+    state binned by the same rule: identical except for cells closer to a bin
+    edge than the two theta values can differ (none at all in FP64 here)."""
+    from oracle import ref_numpy as R
+    modes = forced_modes(F0=4e-5, seed=5)
+    tau0, C = 0.507, 0.15
+    lat = lbm.Lattice(shape, tau0, C, modes, precision=precision, streaming=streaming,
+                      smag_form=1)
+    lat.init(lbm.LBM_INIT_NOISE, 0.03, 13)
+    lat.step(7)                                   # odd: the AA odd layout is read
+    f = lat.populations()
+    _, info = R.collide(f, R.force_field(shape, modes), tau0, C, smag_form=1)
+    theta = (info["tau_e"] - 0.5).ravel()
+    lo, hi, nbins = np.quantile(theta, 0.05), np.quantile(theta, 0.9), 37
+    got = lat.theta_histogram(lo, hi, nbins)
+    ref = _bin_counts(theta, lo, hi, nbins)
+    assert got.sum() == theta.size and got[nbins + 2] == 0
+    # how far the device theta can sit from the oracle's: from the K_t field
+    th_dev = lat.kt_field().astype(np.float64).ravel() / np.sqrt(3.0)
+    delta = 2.0 * np.abs(th_dev - theta).max() + 4e-8 * np.abs(theta).max()
+    if precision == "fp64":
+        delta = 1e-13 * np.abs(theta).max()
+    q = (theta - lo) * (nbins / (hi - lo))
+    near = (np.abs(q - np.round(q)) * (hi - lo) / nbins <= delta).sum()
+    diff = np.abs(got - ref).sum()
+    print(f"{shape} {precision} {streaming}: histogram L1 difference {diff}, "
+          f"cells within {delta:.1e} of an edge {near}", flush=True)
+    assert diff <= 2 * near
+    for bad in ((hi, lo, nbins), (lo, hi, 0), (lo, hi, 4097), (float("nan"), hi, 4)):
+        with pytest.raises(lbm.LbmError):
+            lat.theta_histogram(*bad)
+    lat.close()
