@@ -71,3 +71,16 @@ def test_iso_re_pair_study_small():
         assert all(math.isfinite(v) and v > 0 for v in r["E_kolmogorov"])
         assert all(math.isfinite(v) for v in r["F4"])
     assert res["les"]["theta_min"] > 0
+
+
+def test_c_sweep_study_small():
+    """LES C sweep at 32^3 against a 64^3 DNS (Re 1000, short window): finite
+    spectra, and at the highest common shell more eddy viscosity leaves less energy."""
+    from paper_2512_23116_amd.studies import c_sweep
+    res = c_sweep.run(N_les=32, N_dns=64, Re=1000.0, Cs=(0.0, 0.25), t_start=4, t_end=6,
+                      every=1000, log=lambda m: None)
+    assert res["dns"]["snapshots"] == 3 and len(res["les"]) == 2
+    for r in res["les"]:
+        assert all(math.isfinite(v) and v >= 0 for v in r["E"])
+        assert set(r["ratio_to_dns"]) == {2, 4, 8, 16}
+    assert res["les"][1]["E"][16] < res["les"][0]["E"][16]
