@@ -15,7 +15,8 @@ difference of E_k over the neighbouring snapshots.  Relative error:
 |eps - (<F.u> - dE_k/dt)| / eps, averaged over the window.  Isotropy (Sec. 3.3,
 Tab. isotropy_metrics): mean and standard deviation of the directional energy
 fractions E_i / E and the mean |b_ij| of the off-diagonal anisotropy over the
-window, from the Reynolds stresses lbm_turbulence returns.  Spectral isotropy
+window, from the Reynolds stresses lbm_turbulence returns, and during the spin-up
+the trajectory of the Lumley invariants (xi, eta) and the largest |E_i/E - 1/3|.  Spectral isotropy
 (App. spectral isotropy): the coefficient IC(k) of lbm_spectra_1d, averaged over
 the window, with its mean and largest departure from 1 over 2 <= k <= N/4.
 Spectrum (Sec. 3.4, Fig. DNS_spectra_validation): the window-averaged shell
@@ -45,7 +46,17 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
     lat.init(lbm.LBM_INIT_TGV3D, params.U0 if amp is None else amp)
     t0 = 1000
     tic = time.time()
-    lat.step(t_start * t0 - every)
+    # the spin-up, sampled every `traj_every` t0: the Lumley-triangle trajectory
+    # from the Taylor-Green start (Fig. isotropy_validation)
+    trajectory = []
+    traj_every = max(1, t_start // 40)
+    for t in range(0, t_start, traj_every):
+        if t * t0 > lat.steps:
+            lat.step(t * t0 - lat.steps)
+        tb = lat.turbulence()
+        trajectory.append(dict(t=float(t), xi=tb["lumley_xi"], eta=tb["lumley_eta"],
+                               max_frac_dev=float(np.abs(np.asarray(tb["energy_frac"]) - 1 / 3).max())))
+    lat.step(t_start * t0 - every - lat.steps)
     lat.sync()
     log(f"energy balance {N}^3 Re {Re:g}: reached t/t0 = {t_start - every / t0:g} "
         f"in {time.time() - tic:.1f} s")
@@ -97,6 +108,7 @@ def run(N=128, Re=2500.0, t_start=200, t_end=400, every=1000, amp=None,
         ic_band_mean=float(np.mean(band)), ic_band_max_dev=float(np.max(np.abs(band - 1.0))),
         k_eta=[float(v) for v in k_eta], E_kolmogorov=[float(v) for v in E_kol],
         pope={k: v for k, v in pm.items()},
+        lumley_trajectory=trajectory,
         paper_err={128: "6-7 %", 256: "< 3.5 %", 512: "~1 % (Re 5000)"}.get(N),
         wall_s=time.time() - tic)
     return summary, out

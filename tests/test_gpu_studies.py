@@ -38,6 +38,10 @@ def test_energy_balance_study_small():
     for r in rows:
         assert r["E"] > 0 and r["P"] > 0 and math.isfinite(r["dEdt"])
     assert summary["mean_err_eps_strain"] < 0.2, summary
+    tr = summary["lumley_trajectory"]
+    # the Taylor-Green start has w = 0: E_z = 0, a two-component state
+    assert tr[0]["t"] == 0 and abs(tr[0]["max_frac_dev"] - 1 / 3) < 1e-6
+    assert tr[-1]["max_frac_dev"] < tr[0]["max_frac_dev"]
     assert len(summary["ic_k2_to_kq"]) == 11
     assert all(math.isfinite(v) and v > 0 for v in summary["ic_k2_to_kq"]), summary
     pm = summary["pope"]
