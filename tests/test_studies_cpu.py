@@ -18,3 +18,13 @@ def test_histogram_percentiles_of_a_uniform_sample():
     counts2 = np.zeros(nb + 3, dtype=np.int64)
     counts2[0], counts2[nb + 1] = 10, 10
     assert histogram_percentiles(counts2, lo, hi, (1, 99)) == [lo, hi]
+
+
+def test_c_sweep_combines_les_and_a_separate_reference():
+    from paper_2512_23116_amd.studies.c_sweep import combine
+    les = dict(Re=5000.0, window=[200, 300], dns=None,
+               les=[dict(C=0.1, E=[0.0] + [2.0] * 64)])
+    dns = dict(Re=5000.0, window=[200, 300], dns=dict(N=512, E=[0.0] + [1.0] * 256), les=[])
+    out = combine(les, dns)
+    assert out["dns"]["N"] == 512
+    assert out["les"][0]["ratio_to_dns"] == {k: 2.0 for k in (2, 4, 8, 16, 24, 32, 48, 64)}
