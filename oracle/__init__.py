@@ -19,9 +19,16 @@ Contents
                larger than brute-force sizes and timed as the CPU baseline.
 ``physics``    parameter relations of Sec. 2.1, 2.2, 3.1 and 4 (tau0 from Re,
                F0 from C_f, the K41 worked estimate).
-``stats``      statistics of a per-cell field (two-pass, FP64) and the
-               shell-binned energy spectrum.
+``stats``      statistics of a per-cell field (two-pass, FP64), the
+               shell-binned energy spectrum, structure functions, turbulence
+               scales and isotropy (Sec. 2.2, 3.3, 5.3), the one-dimensional
+               spectra and the spectral isotropy coefficient (App. spectral
+               isotropy).
 
 Every function cites the passage of the paper it follows.  Readings taken
 where the paper is silent or inconsistent are stated where they are used.
+Every function is pinned by tests/test_oracle_pins.py against closed forms,
+invariants, printed values or brute force; the one comparison left unpinned
+is pointwise agreement of long chaotic runs, which are compared through
+statistics only.
 """
