@@ -8,9 +8,10 @@ the small scales, and C = 0.16 lies between.  Setup as in Sec. 3.1: U0 = 0.043,
 tau0 = 1/2 + 3 U0 N / Re, three-mode forcing of eq. forcing_pattern with
 F0 = C_f U0^2 / N (C_f = 0.2), Taylor-Green start of amplitude U0, t0 = 1000
 iterations on every grid; nu_t = C^2 |S| (the form that reproduces the
-paper's theta statistics).  The reference DNS here is 256^3 at the same Re
-(the paper does not state the resolution of its reference curve), run with
-two steps per pass.
+paper's theta statistics).  The reference DNS is 512^3 at the same Re (the
+paper does not state the resolution of its reference curve; 256^3 is itself
+under-resolved at Re = 5000 and carries too much energy at high k), run with
+two steps per pass: about 16 minutes on one MI355X, the LES runs 15 s each.
 
 Both grids span the same 2 pi box, so shell k is the same wavenumber on both
 and E(k) (shell energy of 1/2 |u_hat|^2 in lattice velocity units, U0 the same
@@ -18,6 +19,7 @@ on both grids) compares directly.  Spectra are averaged over t/t0 in
 [t_start, t_end]; the study reports E(k) and the ratio LES / DNS.
 
     python -m paper_2512_23116_amd.studies.c_sweep [--t-end 300]
+    python -m paper_2512_23116_amd.studies.c_sweep --N-dns 0 > les.json       # LES only
     python -m paper_2512_23116_amd.studies.c_sweep --N-dns 512 --Cs "" > dns512.json
     python -m paper_2512_23116_amd.studies.c_sweep --combine les.json dns512.json
 """
@@ -76,7 +78,7 @@ def ratios(les, dns):
     return {int(k): float(El[k] / Ed[k]) for k in RATIO_K if k < El.size}
 
 
-def run(N_les=128, N_dns=256, Re=5000.0, Cs=(0.0, 0.1, 0.16, 0.25), t_start=200, t_end=300,
+def run(N_les=128, N_dns=512, Re=5000.0, Cs=(0.0, 0.1, 0.16, 0.25), t_start=200, t_end=300,
         every=2000, log=lambda m: print(m, file=sys.stderr, flush=True)):
     """Reference DNS (N_dns = 0: none) and the LES runs for each C in Cs."""
     dns = spectrum_run(N_dns, Re, 0.0, t_start, t_end, every, log, "dns") if N_dns else None
@@ -101,7 +103,7 @@ def combine(les_result, dns_result):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--N-les", type=int, default=128)
-    ap.add_argument("--N-dns", type=int, default=256, help="0: no reference DNS")
+    ap.add_argument("--N-dns", type=int, default=512, help="0: no reference DNS")
     ap.add_argument("--Cs", default="0,0.1,0.16,0.25", help="comma list; empty: no LES")
     ap.add_argument("--Re", type=float, default=5000.0)
     ap.add_argument("--t-start", type=int, default=200)
