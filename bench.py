@@ -69,13 +69,11 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
     stats = [lat.stats()] if warmup == 0 else []
     kt_slices, spectra = [], []
     lat.step(warmup)
-    kt_buf = None
     if maps:
         # one-time set-up outside the timed region: the FFT plan and the analysis
-        # buffers, and a page-locked host buffer for the K_t field
+        # and staging buffers
         lat.spectrum(N // 2)
-        kt_buf = torch.empty(N ** 3, dtype=torch.float32, pin_memory=True).numpy()
-        lat.kt_field(out=kt_buf)
+        lat.kt_slice(N // 2)
     lat.sync()
     events = []
     torch.cuda.synchronize()
@@ -93,7 +91,7 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
         if diag_every and done % diag_every == 0:
             stats.append(lat.stats())
             if maps:
-                kt_slices.append(lat.kt_field(out=kt_buf)[N // 2].copy())
+                kt_slices.append(lat.kt_slice(N // 2))
                 spectra.append(lat.spectrum(N // 2))
     lat.sync()
     torch.cuda.synchronize()
@@ -340,7 +338,7 @@ def main():
                          f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
                          f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
                          f"forcing, 1e-3 noise start; every {args.diag_every} steps K_t "
-                         "statistics, K_t map (mid-z slice to host) and energy spectrum, "
+                         "statistics, K_t map (mid-z plane to host) and energy spectrum, "
                          "all inside the timed region"),
             "N": args.N, "precision": args.precision, "streaming": args.streaming,
             "steps_per_graph": args.steps_per_graph, "parallelism": "single GPU",

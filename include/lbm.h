@@ -198,6 +198,12 @@ lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out);
  * Synchronises. */
 lbm_status lbm_kt_field(lbm_handle* h, float* kt);
 
+/* The K_t map of one plane (Sec. 5.1 shows such slices): kt[x + nx y] = K_t of
+ * cell (x, y, z), host float[nx*ny], the same values as lbm_kt_field for that
+ * plane.  Only the plane is evaluated and copied.  0 <= z < nz, else
+ * LBM_ERR_INVALID_ARG.  Synchronises. */
+lbm_status lbm_kt_slice(lbm_handle* h, int32_t z, float* kt);
+
 /* Canonical full populations f[a * ncells + c] of the current state (host,
  * 19 * ncells doubles).  Synchronises. */
 lbm_status lbm_get_populations(lbm_handle* h, double* f);

@@ -496,6 +496,23 @@ lbm_status lbm_kt_field(lbm_handle* h, float* kt) {
     return st;
 }
 
+lbm_status lbm_kt_slice(lbm_handle* h, int32_t z, float* kt) {
+    if (!h || !kt) return h ? fail(h, LBM_ERR_INVALID_ARG, "kt is NULL") : LBM_ERR_INVALID_ARG;
+    if (z < 0 || (uint32_t)z >= h->args.nz)
+        return fail(h, LBM_ERR_INVALID_ARG, "z = %d outside 0..%u", z, h->args.nz - 1);
+    if (!h->initialized) return fail(h, LBM_ERR_STATE, "state not initialised");
+    const size_t n = h->args.nxy;
+    lbm_status st = ensure_staging(h, (n + 1) / 2);
+    if (st != LBM_OK) return st;
+    hipError_t e = launch_ktslice(h->cfg.precision, current_pattern(h), current_args(h),
+                                  (uint32_t)z, (float*)h->staging, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "kt slice kernel");
+    HIPCHK(h, hipMemcpyAsync(kt, h->staging, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    st = sync(h);
+    trim_staging(h);
+    return st;
+}
+
 lbm_status lbm_get_populations(lbm_handle* h, double* f) {
     if (!h || !f) return h ? fail(h, LBM_ERR_INVALID_ARG, "f is NULL") : LBM_ERR_INVALID_ARG;
     if (!h->initialized) return fail(h, LBM_ERR_STATE, "state not initialised");

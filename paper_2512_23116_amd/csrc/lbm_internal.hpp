@@ -60,6 +60,8 @@ hipError_t launch_diag(int precision, int pat, const LatticeArgs& L, double* par
 hipError_t launch_moments(int precision, int pat, const LatticeArgs& L, double* rho, double* u,
                           hipStream_t s);
 hipError_t launch_ktfield(int precision, int pat, const LatticeArgs& L, float* kt, hipStream_t s);
+hipError_t launch_ktslice(int precision, int pat, const LatticeArgs& L, uint32_t z, float* kt,
+                          hipStream_t s);
 hipError_t launch_theta_hist(int precision, int pat, const LatticeArgs& L, double lo, double inv_w,
                              int nbins, unsigned long long* counts, hipStream_t s);
 hipError_t launch_gather_plane(int precision, int pat, const LatticeArgs& L, int i, double* out,

@@ -181,6 +181,15 @@ __global__ __launch_bounds__(256) void k_ktfield(LatticeArgs L, float* kt) {
     kt[cell] = (float)(1.7320508075688772 * theta);   // K_t = sqrt(3) theta, ell = delta_x
 }
 
+// K_t of the cells of plane z: kt[x + nx y].
+template <class Cd, int PAT>
+__global__ __launch_bounds__(256) void k_ktslice(LatticeArgs L, uint32_t z, float* kt) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= L.nxy) return;
+    const double theta = cell_theta<Cd, PAT>(L, i + L.nxy * z);
+    kt[i] = (float)(1.7320508075688772 * theta);
+}
+
 // Fixed-bin histogram of theta: counts[0] below lo, counts[1 + b] for
 // b = floor((theta - lo) * inv_w) in 0..nbins-1, counts[nbins + 1] at or above
 // the top edge, counts[nbins + 2] non-finite.  Per-block LDS counts, then one
@@ -442,6 +451,16 @@ hipError_t launch_ktfield(int precision, int pat, const LatticeArgs& L, float* k
         using Cd = decltype(cd);
         constexpr int P = decltype(pt)::value;
         hipLaunchKernelGGL((k_ktfield<Cd, P>), grid_for(L.ncell), dim3(256), 0, s, L, kt);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_ktslice(int precision, int pat, const LatticeArgs& L, uint32_t z, float* kt,
+                          hipStream_t s) {
+    return dispatch(precision, pat, [&](auto cd, auto pt) {
+        using Cd = decltype(cd);
+        constexpr int P = decltype(pt)::value;
+        hipLaunchKernelGGL((k_ktslice<Cd, P>), grid_for(L.nxy), dim3(256), 0, s, L, z, kt);
         return hipGetLastError();
     });
 }

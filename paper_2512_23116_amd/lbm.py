@@ -29,7 +29,7 @@ STREAMING = {"aa": LBM_STREAM_AA, "ab": LBM_STREAM_AB}
 # C-ABI entry points every build must export (checked by the CPU tests).
 EXPORTS = (
     "lbm_config_default", "lbm_required_bytes", "lbm_create", "lbm_init_seeded", "lbm_step",
-    "lbm_moments", "lbm_kt_stats", "lbm_kt_field", "lbm_get_populations",
+    "lbm_moments", "lbm_kt_stats", "lbm_kt_field", "lbm_kt_slice", "lbm_get_populations",
     "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_steps_done",
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
@@ -137,6 +137,7 @@ def lib():
         "lbm_moments": (ctypes.c_int, [H, dp, dp]),
         "lbm_kt_stats": (ctypes.c_int, [H, ctypes.POINTER(lbm_stats)]),
         "lbm_kt_field": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_float)]),
+        "lbm_kt_slice": (ctypes.c_int, [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
         "lbm_get_populations": (ctypes.c_int, [H, dp]),
         "lbm_set_populations": (ctypes.c_int, [H, dp]),
         "lbm_sample_populations": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int64),
@@ -241,6 +242,12 @@ def lbm_kt_field(h, ncell, out=None):
             raise ValueError("out must be a writeable C-contiguous float32 array of ncell elements")
         kt = out.reshape(-1)
     _check(lib().lbm_kt_field(h, kt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), h)
+    return kt
+
+
+def lbm_kt_slice(h, z, nxy):
+    kt = np.empty(nxy, dtype=np.float32)
+    _check(lib().lbm_kt_slice(h, z, kt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), h)
     return kt
 
 
@@ -428,6 +435,10 @@ class Lattice:
 
     def theta_histogram(self, lo, hi, nbins):
         return lbm_theta_histogram(self.handle, lo, hi, nbins)
+
+    def kt_slice(self, z):
+        """K_t of plane z as an (ny, nx) array."""
+        return lbm_kt_slice(self.handle, z, self.shape[1] * self.shape[2]).reshape(self.shape[1:])
 
     def spectrum(self, kmax):
         return lbm_spectrum(self.handle, kmax)

@@ -134,6 +134,8 @@ def test_null_handles_are_rejected_without_touching_a_device(lbm):
         lambda: L.lbm_get_populations(None, dp),
         lambda: L.lbm_set_populations(None, dp),
         lambda: L.lbm_spectrum(None, 4, dp),
+        lambda: L.lbm_kt_slice(None, 0, np.zeros(4, np.float32).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_float))),
         lambda: L.lbm_theta_histogram(None, 0.0, 1.0, 4,
                                       np.zeros(8, np.int64).ctypes.data_as(
                                           ctypes.POINTER(ctypes.c_int64))),

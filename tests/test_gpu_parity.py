@@ -233,6 +233,12 @@ def test_kt_stats_and_fields_match_oracle(lbm, orc, precision, tol):
     import torch
     pinned = torch.empty(kt.size, dtype=torch.float32, pin_memory=True).numpy()
     assert np.array_equal(lat.kt_field(out=pinned), kt)
+    # one plane at a time: the same values
+    for z in sorted({0, shape[0] // 2, shape[0] - 1}):
+        assert np.array_equal(lat.kt_slice(z), kt[z])
+    for z in (-1, shape[0]):
+        with pytest.raises(lbm.LbmError):
+            lat.kt_slice(z)
 
 
 def test_stats_are_bitwise_reproducible_and_C0_is_dns(lbm):
