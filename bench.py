@@ -40,7 +40,7 @@ def counter_traffic(workload_key, family="k_step"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current sources of that kernel (else None)."""
     from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_forced_hit_100_800.txt")
     if not os.path.exists(path):
         return None
     sha = kernel_source_sha(family)

@@ -1,7 +1,7 @@
 """Summarise rocprofv3 output for the step kernels.
 
     python -m paper_2512_23116_amd.rocprof_summary --trace DIR [--fetch DIR --write DIR]
-        [--cmd "the profiled command"] [--traffic-out profiles/hbm_traffic.txt]
+        [--cmd "the profiled command"] [--traffic-out profiles/hbm_traffic_step_kernels_forced_hit_100_800.txt]
 
 ``--trace`` is a ``rocprofv3 --kernel-trace --stats --output-format csv`` output
 directory: per-kernel launch counts and durations are listed per grid size

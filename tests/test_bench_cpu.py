@@ -17,7 +17,7 @@ def test_counter_traffic_is_keyed_by_kernel_sources():
     sys.path.insert(0, ROOT)
     import bench
     from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_forced_hit_100_800.txt")
     rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
     assert rows, "no counter rows"
     for key, sha, fetch, write, fam, *_ in rows:
