@@ -183,7 +183,10 @@ def run_serving(n_req, steps, seed=2024):
     res = serving.serve(reqs, eng, max_slots=16, hbm_budget=80e9)
     eng.close()
     return dict(requests=n_req, steps_each=steps, arrival_rate_per_s=rate,
-                p50_s=res["p50_s"], p99_s=res["p99_s"], aggregate_mlups=res["aggregate_mlups"],
+                p50_s=res["p50_s"], p99_s=res["p99_s"],
+                wait_p50_s=res["wait_p50_s"], wait_p99_s=res["wait_p99_s"],
+                service_p50_s=res["service_p50_s"], service_p99_s=res["service_p99_s"],
+                aggregate_mlups=res["aggregate_mlups"],
                 busy_mlups=res["busy_mlups"], busy_frac=res["busy_frac"], failed=res["failed"],
                 capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80,
                 group_mb=serving.GROUP_BYTES >> 20)

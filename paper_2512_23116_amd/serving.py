@@ -220,7 +220,10 @@ def serve(requests, engine, max_slots=16, hbm_budget=80e9, keep_state=False, clo
                 still.append(r)
         active = still
     t_end = clock() - t0
-    lat = np.array([r.latency for r in requests if r.error is None and r.latency is not None])
+    done = [r for r in requests if r.error is None and r.latency is not None]
+    lat = np.array([r.latency for r in done])
+    wait = np.array([r.admit - r.arrival for r in done])
+    service = np.array([r.complete - r.admit for r in done])
     first = min(r.arrival for r in requests) if requests else 0.0
     span = max(t_end - first, 1e-12)
     return dict(
@@ -228,6 +231,11 @@ def serve(requests, engine, max_slots=16, hbm_budget=80e9, keep_state=False, clo
         p50_s=float(np.percentile(lat, 50)) if lat.size else None,
         p99_s=float(np.percentile(lat, 99)) if lat.size else None,
         mean_s=float(lat.mean()) if lat.size else None,
+        # latency = queueing (arrival -> admission) + service (admission -> completion)
+        wait_p50_s=float(np.percentile(wait, 50)) if wait.size else None,
+        wait_p99_s=float(np.percentile(wait, 99)) if wait.size else None,
+        service_p50_s=float(np.percentile(service, 50)) if service.size else None,
+        service_p99_s=float(np.percentile(service, 99)) if service.size else None,
         wall_s=t_end, busy_s=busy, busy_frac=busy / span,
         cell_updates=cell_updates,
         aggregate_mlups=cell_updates / span / 1e6,

@@ -44,9 +44,14 @@ def test_hbm_budget_forces_queueing():
     reqs = [_req(i, 32, 0.0, steps=64) for i in range(4)]
     one = reqs[0].state_bytes
     eng = FakeEngine(rate=1e10, steps_per_graph=64)
-    serve(reqs, eng, max_slots=16, hbm_budget=2 * one)
+    res = serve(reqs, eng, max_slots=16, hbm_budget=2 * one)
     assert max(len(c) for c in eng.calls) == 2
     assert all(r.done_steps == 64 for r in reqs)
+    # half the requests waited for memory: the latency splits into queueing + service
+    assert res["wait_p50_s"] >= 0 and res["wait_p99_s"] > 0
+    assert res["service_p99_s"] > 0
+    for r in reqs:
+        assert abs((r.admit - r.arrival) + (r.complete - r.admit) - r.latency) < 1e-12
 
 
 def test_oversized_and_failing_requests_fail_alone():
