@@ -67,3 +67,21 @@ def test_serving_under_a_tight_budget_matches_alone_and_oracle(orc):
             assert err <= 1.5e-4
         for lat in (got, alone, plain):
             lat.close()
+
+
+def test_cache_groups_give_the_same_results_as_one_batch():
+    """Several batched calls per step call (tiny group size) against one call over
+    all slots: every request's final state is bitwise the same."""
+    from paper_2512_23116_amd import lbm, serving
+    lbm.lib()
+    states = {}
+    for group_bytes in (None, 300_000):
+        reqs = serving.make_requests(8, seed=91, steps=96, sizes=(16, 24, 32))
+        assert sum(r.state_bytes for r in reqs) > 3 * 300_000      # several groups per call
+        eng = serving.GpuEngine(max_slots=8, steps_per_graph=32, group_bytes=group_bytes)
+        res = serving.serve(reqs, eng, max_slots=8, hbm_budget=1e12, keep_state=True)
+        eng.close()
+        assert res["failed"] == 0
+        states[group_bytes] = {r.rid: r.result["state"] for r in reqs}
+    for rid, s in states[None].items():
+        np.testing.assert_array_equal(states[300_000][rid], s)
