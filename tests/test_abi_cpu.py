@@ -1,5 +1,6 @@
 """Host-side checks of the C-ABI library (no GPU work is launched)."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -162,3 +163,47 @@ def test_kt_field_out_buffer_is_checked_before_the_call(lbm):
     for out in bad:
         with pytest.raises(ValueError):
             lbm.lbm_kt_field(None, 8, out)
+
+
+def test_random_configs_never_crash_and_sizes_follow_the_layout(lbm):
+    """Property test over random, mostly invalid configurations: the host-side
+    checks either reject them (size 0, INVALID_ARG, no handle) or the state size is
+    19 planes of round_up(ncell, 64) + 1728 elements (twice for A/B)."""
+    from hypothesis import given, settings, strategies as st
+    nan, inf = float("nan"), float("inf")
+    floats = st.one_of(st.floats(-3.0, 3.0), st.sampled_from([nan, inf, -inf, 0.5, 0.0, 2.0]))
+
+    @settings(max_examples=300, deadline=None, derandomize=True)
+    @given(nx=st.integers(-2, 1400), ny=st.integers(-2, 1400), nz=st.integers(-2, 1400),
+           precision=st.integers(-1, 4), streaming=st.integers(-1, 2),
+           smag_form=st.integers(-1, 2), tau_mode=st.integers(-1, 2),
+           temporal_block=st.integers(-1, 3), spg=st.integers(-2, 2050),
+           tau0=floats, C=floats, rho0=floats, s_m=floats, scale=floats)
+    def check(nx, ny, nz, precision, streaming, smag_form, tau_mode, temporal_block, spg,
+              tau0, C, rho0, s_m, scale):
+        c = lbm.lbm_config_default()
+        c.nx, c.ny, c.nz = nx, ny, nz
+        c.precision, c.streaming, c.smag_form = precision, streaming, smag_form
+        c.tau_mode, c.temporal_block, c.steps_per_graph = tau_mode, temporal_block, spg
+        c.tau0, c.smag_C, c.rho0, c.s_m, c.storage_scale = tau0, C, rho0, s_m, scale
+        size = lbm.lbm_required_bytes(c)
+        if size == 0:
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.lbm_create(c)
+            assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+            return
+        # accepted: every rule of the header holds
+        ncell = nx * ny * nz
+        assert min(nx, ny, nz) >= 1 and ncell < 2 ** 31
+        assert tau0 > 0.5 and C >= 0.0 and rho0 > 0.0 and 0.0 < s_m < 2.0
+        assert smag_form in (0, 1) and tau_mode in (0, 1) and streaming in (0, 1)
+        assert spg == 0 or (2 <= spg <= 1024 and spg % 2 == 0)
+        assert scale == 0.0 or (scale > 0.0 and math.frexp(scale)[0] == 0.5)
+        if temporal_block == 2:
+            assert streaming == 1 and precision != 0 and spg % 4 == 0
+        b = {0: 8, 1: 4, 2: 2, 3: 2}[precision]
+        plane = (ncell + 63) // 64 * 64 + 1728
+        assert plane * b < 2 ** 32
+        assert size == 19 * plane * b * (2 if streaming == 1 else 1)
+
+    check()
