@@ -78,9 +78,14 @@ def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None
                          p50=float(np.median(th)), p95=float(np.percentile(th, 95)),
                          p99=float(np.percentile(th, 99)), max=float(th.max()),
                          min=float(th.min()), slice_mean=float(sl.mean()),
-                         slice_p95=float(np.percentile(sl, 95)), energy=st["energy"],
-                         flat=st["theta_flat"]))
+                         slice_p95=float(np.percentile(sl, 95)),
+                         slice_p99=float(np.percentile(sl, 99)), slice_max=float(sl.max()),
+                         energy=st["energy"], flat=st["theta_flat"]))
     lat.close()
+    # the paper's maps: slice k = N/2 at t/t0 = 200 and 600 (Fig. tau_maps)
+    maps = {str(int(r["t"])): dict(mean=r["slice_mean"], p95=r["slice_p95"], p99=r["slice_p99"],
+                                   max=r["slice_max"])
+            for r in rows if r["t"] in (200.0, 600.0)}
     win = {k: float(np.mean([r[k] for r in rows])) for k in rows[0] if k != "t"}
     win["max"] = float(max(r["max"] for r in rows))
     win["min"] = float(min(r["min"] for r in rows))
@@ -90,6 +95,7 @@ def run(smag_form=0, C=0.13, t_start=200, t_end=600, every=2000, N=100, amp=None
                            window=[t_start, t_end], snapshots=len(rows), every=every),
                 window_mean=win, normalised_mean=win["mean"] / theta0,
                 normalised_p95=win["p95"] / theta0,
+                slice_maps=maps,
                 histogram=dict(lo=0.0, hi=hist_hi, bins=hist_bins,
                                counts=[int(v) for v in hist],
                                pooled_percentiles=dict(zip(("p5", "p50", "p95", "p99"), hp))),
