@@ -361,7 +361,13 @@ def make_modes(modes):
 
 
 class Lattice:
-    """One lattice on the current HIP device: owns its handle and torch buffer."""
+    """One lattice on the current HIP device: owns its handle and torch buffer.
+
+    shape is (nz, ny, nx); modes are (k, amp, phase) triples of the body force;
+    precision "fp64" | "fp32" | "fp16" | "bf16"; streaming "aa" | "ab".  Arrays
+    come back as (…, nz, ny, nx) with x fastest, the canonical pre-collision
+    state after `steps` steps.  Every method is one C-ABI call (include/lbm.h).
+    """
 
     def __init__(self, shape, tau0, C, modes=(), precision="fp32", streaming="aa",
                  smag_form=0, steps_per_graph=64, storage_scale=0.0, stream=None, rho0=1.0,
@@ -403,37 +409,50 @@ class Lattice:
         self.handle = lbm_create(cfg)
 
     def init(self, kind, amp, seed=0):
+        """lbm_init_seeded: equilibrium of an LBM_INIT_* velocity field; steps = 0."""
         lbm_init_seeded(self.handle, kind, amp, seed)
         return self
 
     def step(self, n=1):
+        """lbm_step: n time steps, asynchronous on the lattice's stream."""
         lbm_step(self.handle, n)
         return self
 
     def sync(self):
+        """lbm_synchronize: wait for the lattice's stream."""
         lbm_synchronize(self.handle)
 
     @property
     def steps(self):
+        """Time steps done since the last init / load."""
         return lbm_steps_done(self.handle)
 
     def populations(self):
+        """lbm_get_populations: full f, (19, nz, ny, nx) FP64."""
         return lbm_get_populations(self.handle, self.ncell).reshape((19,) + self.shape)
 
     def set_populations(self, f):
+        """lbm_set_populations: replace the state by full f, (19, ...) FP64."""
         lbm_set_populations(self.handle, np.asarray(f).reshape(19, -1))
 
     def moments(self):
+        """lbm_moments: rho (nz, ny, nx) and the Guo velocity u (3, nz, ny, nx)."""
         rho, u = lbm_moments(self.handle, self.ncell)
         return rho.reshape(self.shape), u.reshape((3,) + self.shape)
 
     def stats(self, allow_unstable=False):
+        """lbm_kt_stats: dict of the FP64 theta / K_t statistics, mass, momentum,
+        energy and the energy-balance sums; raises on a non-finite state unless
+        allow_unstable."""
         return lbm_kt_stats(self.handle, allow_unstable)
 
     def kt_field(self, out=None):
+        """lbm_kt_field: K_t per cell, (nz, ny, nx) float32 (into `out` if given)."""
         return lbm_kt_field(self.handle, self.ncell, out).reshape(self.shape)
 
     def theta_histogram(self, lo, hi, nbins):
+        """lbm_theta_histogram: int64[nbins + 3] = [below lo, bins..., at or above
+        hi, non-finite]."""
         return lbm_theta_histogram(self.handle, lo, hi, nbins)
 
     def kt_slice(self, z):
@@ -441,27 +460,35 @@ class Lattice:
         return lbm_kt_slice(self.handle, z, self.shape[1] * self.shape[2]).reshape(self.shape[1:])
 
     def spectrum(self, kmax):
+        """lbm_spectrum: shell spectrum E(0..kmax)."""
         return lbm_spectrum(self.handle, kmax)
 
     def spectra_1d(self, kmax, with_ic=True):
+        """lbm_spectra_1d: (E[c, a, k] of shape (3, 3, kmax+1), IC(k) or None)."""
         return lbm_spectra_1d(self.handle, kmax, with_ic)
 
     def structure_functions(self, rs):
+        """lbm_structure_functions: (len(rs), 6) moments of longitudinal increments."""
         return lbm_structure_functions(self.handle, rs)
 
     def turbulence(self, kmax=0):
+        """lbm_turbulence: dict of the turbulence scales and isotropy measures."""
         return lbm_turbulence(self.handle, kmax)
 
     def save(self):
+        """lbm_save_state: (state bytes as uint8 array, steps)."""
         return lbm_save_state(self.handle)
 
     def load(self, buf, steps):
+        """lbm_load_state: restore a saved state and its step count."""
         lbm_load_state(self.handle, buf, steps)
 
     def sample(self, cells):
+        """lbm_sample_populations: full f of the listed cell indices, (n, 19)."""
         return lbm_sample_populations(self.handle, cells)
 
     def close(self):
+        """lbm_destroy; also drops the torch buffer.  Safe to call twice."""
         if getattr(self, "handle", None) is not None and self.handle.value:
             lbm_destroy(self.handle)
             self.handle = None
