@@ -210,7 +210,8 @@ def profile_run(lbm, params, args):
         runs += [(args.large_N, p, "aa", 0, 4), (args.large_N, p, "ab", 0, 4),
                  (args.large_N, p, "ab", 2, 8)]
         if not args.no_precision:
-            runs += [(args.large_N, "fp16", "aa", 0, 4), (args.large_N, "bf16", "aa", 0, 4)]
+            runs += [(args.large_N, "fp16", "aa", 0, 4), (args.large_N, "bf16", "aa", 0, 4),
+                     (args.large_N, "fp16", "ab", 2, 8)]
     for N, prec, streaming, tb, steps in runs:
         run_lattice(lbm, params, N, prec, streaming, steps, 2, 0, spg=0, tb=tb)
         log(f"profile: {N}^3 {prec} {streaming}{' two-step' if tb else ''}, "
@@ -308,6 +309,27 @@ def main():
                 "vs_fp32": precision_errors(pr, large, args.large_N)}
             log(f"precision: {prec} {pr['mlups']:.0f} MLUPS, {rr['frac']:.3f} of HBM peak, "
                 f"K_t mean rel err {precision[prec]['vs_fp32']['kt_rel_err_max']['mean']:.2e}")
+        # FP16 storage with two time steps per pass (A/B): the fastest form
+        log(f"precision: {args.large_N}^3 fp16 A/B two steps per pass, {args.large_steps} steps")
+        pr = run_lattice(lbm, params, args.large_N, "fp16", "ab", args.large_steps, 0,
+                         args.diag_every, args.steps_per_graph, tb=2,
+                         final_spectrum=args.large_N // 4)
+        rr = pr["roofline"]
+        pass_us = 2 * pr["avg_launch_us"]
+        own = rr["bytes_per_launch"] / (pass_us * 1e-6) / 1e9
+        precision["fp16_two_step"] = {
+            "workload": (f"forced HIT LES {args.large_N}^3, fp16 deviations, A/B with two time "
+                         "steps per pass (intermediate level in LDS)"),
+            "mlups": round(pr["mlups"], 1), "steps": pr["steps"],
+            "ms_per_step": round(pr["ms_per_step"], 4),
+            "roofline": {"bound": "hbm", "achieved": round(own, 1), "peak": rr["peak"],
+                         "unit": "GB/s", "frac": round(own / rr["peak"], 4),
+                         "traffic": counter_traffic(f"{args.large_N}_fp16_ab_tb2", "k_step_tb2"),
+                         "avg_launch_us": round(pass_us, 3)},
+            "step_equivalent": {"achieved": round(rr["achieved"], 1), "frac": round(rr["frac"], 4)},
+            "vs_fp32": precision_errors(pr, large, args.large_N)}
+        log(f"precision: fp16 two steps per pass {pr['mlups']:.0f} MLUPS, "
+            f"{rr['frac']:.3f} of the single-step HBM roofline")
 
     serving = None
     if not args.no_serving:

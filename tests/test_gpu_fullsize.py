@@ -102,3 +102,62 @@ def test_fp64_256_one_step_sampled(lbm, orc):
     print(f"256^3 fp64: sampled one-step error {err:.3e}", flush=True)
     assert err <= 1e-12
     lat.close()
+
+
+def sampled_two_step_check(lat, olat, shape, pts):
+    """f_i(x, n+2) from one two-step pass against the oracle: every cell
+    y - c_j upstream of y = x - c_i collided at step n, streamed to y, y collided
+    at step n+1 and streamed to x."""
+    need = sorted({_cell(x - OL.C[i][0] - OL.C[j][0], y - OL.C[i][1] - OL.C[j][1],
+                         z - OL.C[i][2] - OL.C[j][2], shape)
+                   for (x, y, z) in pts for i in range(19) for j in range(19)})
+    before = dict(zip(need, lat.sample(np.array(need))))
+    lat.step(2)                      # one pass of the two-step kernel
+    after = lat.sample(np.array([_cell(x, y, z, shape) for (x, y, z) in pts]))
+    nz, ny, nx = shape
+    first = {}
+
+    def collided(cx, cy, cz):        # post-collision f at step n of a cell
+        c = _cell(cx, cy, cz, shape)
+        if c not in first:
+            F = olat.force_at(cx % nx, cy % ny, cz % nz)
+            first[c] = olat.collide_cell(before[c], F)[0]
+        return first[c]
+
+    worst = 0.0
+    scale = np.abs(after - OL.W).max()
+    for k, (x, y, z) in enumerate(pts):
+        for i in range(19):
+            yx, yy, yz = x - OL.C[i][0], y - OL.C[i][1], z - OL.C[i][2]
+            g = np.array([collided(yx - OL.C[j][0], yy - OL.C[j][1], yz - OL.C[j][2])[j]
+                          for j in range(19)])      # f(y, n+1), pre-collision
+            F = olat.force_at(yx % nx, yy % ny, yz % nz)
+            pred = olat.collide_cell(g, F)[0][i]
+            worst = max(worst, abs(pred - after[k, i]))
+    return worst / scale
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16", 2e-3)])
+def test_two_step_pass_fullsize_against_the_oracle(lbm, orc, precision, tol):
+    """800^3 A/B with two steps per pass, 64-step graphs (the benchmark's
+    configuration): sampled cells after one more pass against two oracle steps.
+    FP16 rounds the intermediate level through its codec, hence the wider bar."""
+    N = 800
+    shape = (N, N, N)
+    cfg = params.forced_hit(N)
+    lat = lbm.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], precision=precision,
+                      streaming="ab", smag_form=cfg["smag_form"], steps_per_graph=64,
+                      temporal_block=2)
+    lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
+    st0 = lat.stats()
+    lat.step(130)                    # two graph replays and a pass
+    st1 = lat.stats()
+    olat = orc.Lattice(shape, cfg["tau0"], cfg["C"], cfg["modes"], smag_form=cfg["smag_form"])
+    err = sampled_two_step_check(lat, olat, shape, _sample_cells(shape, 24, 3))
+    drift = abs(st1["mass"] - st0["mass"]) / st0["mass"]
+    print(f"800^3 {precision} two-step pass: sampled error {err:.3e}, mass drift {drift:.2e}",
+          flush=True)
+    assert err <= tol
+    assert drift <= (1e-9 if precision == "fp32" else 1e-8)
+    assert st1["n_nonfinite"] == 0
+    lat.close()
