@@ -13,8 +13,8 @@ state resident in HBM.
 Beside it the same line carries: the roofline of the step kernel (algorithmic
 bytes 2 * 19 * 4 per cell update over its average launch time, from HIP events
 on the kernel's stream), the 800^3 FP32 runs (AA, A/B, A/B with two steps per
-pass), the 800^3 FP16 / BF16 storage runs with their K_t-statistics and
-spectral errors against the FP32 run, the batched-serving run (p50/p99
+pass), the 800^3 FP16 / BF16 storage runs (and FP16 with two steps per pass)
+with their K_t-statistics and spectral errors against the FP32 run, the batched-serving run (p50/p99
 completion latency and aggregate MLUPS), and the FP64 C oracle timed on the
 host cores on a bounded sample.
 """
