@@ -20,11 +20,13 @@ struct CdF32 { using T = float;    using R = float;  };
 struct CdF16 { using T = _Float16; using R = float;  };
 struct CdBF16 { using T = uint16_t; using R = float; };
 
+// float -> bf16 with round-to-nearest-even.  gfx950 has a conversion
+// instruction for it (v_cvt_pk_bf16_f32, emitted for this cast): one
+// instruction where the integer rounding took six, bit-identical to it for
+// every finite input (NaN stays NaN).
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const __bf16 h = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, h);
 }
 
 template <class Cd>
