@@ -110,11 +110,21 @@ __device__ __forceinline__ int32_t off_minus_rt(int i, const Nbr& n) {
 __device__ __forceinline__ uint32_t block_id(const LatticeArgs& L) {
     uint32_t b = blockIdx.x;
     if (L.xcd_remap) {
-        // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs;
-        // give each XCD one contiguous range of blocks instead.
+        // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.
+        // xcd_remap = 1: each XCD takes one contiguous range of blocks (best while
+        // the state sits in the last-level cache); K >= 2: the XCDs take turns on
+        // chunks of K consecutive blocks, so all of them stream through nearby
+        // addresses of each plane (better once the state is in HBM).  A last,
+        // incomplete round of 8 K blocks keeps the dispatch order.
         const uint32_t G = gridDim.x, xcd = b & 7u, local = b >> 3;
-        const uint32_t per = G >> 3, rem = G & 7u;
-        b = xcd * per + (xcd < rem ? xcd : rem) + local;
+        const uint32_t K = (uint32_t)L.xcd_remap;
+        if (K >= 2) {
+            const uint32_t full = G / (8u * K) * (8u * K);
+            if (b < full) b = ((local / K) * 8u + xcd) * K + local % K;
+        } else {
+            const uint32_t per = G >> 3, rem = G & 7u;
+            b = xcd * per + (xcd < rem ? xcd : rem) + local;
+        }
     }
     return b;
 }

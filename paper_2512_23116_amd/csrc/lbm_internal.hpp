@@ -43,7 +43,8 @@ struct LatticeArgs {
     double tau0, rho0;
     double sigma, inv_sigma; // FP16/BF16 storage scale
     float sigma_f, inv_sigma_f;
-    int32_t xcd_remap;       // remap block ids so each XCD walks a contiguous range
+    int32_t xcd_remap;       // step-kernel block order: 0 dispatch order, 1 one contiguous
+                             // range per XCD, K >= 2 chunks of K blocks in turn
     int32_t nt_mode;         // step kernel: bit 1 non-temporal stores
     uint32_t elem_bytes;     // bytes per stored population
     uint32_t pad_;
