@@ -181,14 +181,6 @@ lbm_status capture_graph(lbm_handle* h) {
 
 namespace lbm {
 
-DivMagic make_div_magic(uint32_t d) {
-    uint32_t L = 0;
-    while ((1ull << L) < d) ++L;
-    const unsigned __int128 one = 1;
-    const unsigned __int128 M = ((one << (32 + L)) + d - 1) / d;   // in [2^32, 2^33)
-    return DivMagic{(uint32_t)(M - (one << 32)), L};
-}
-
 int current_pattern(const lbm_handle* h) {
     if (h->cfg.streaming == LBM_STREAM_AB) return PAT_AB;
     return (h->steps & 1) ? PAT_AA_ODD : PAT_AA_EVEN;

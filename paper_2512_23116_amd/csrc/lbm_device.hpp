@@ -52,10 +52,6 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-__device__ __forceinline__ uint32_t fast_div(uint32_t n, DivMagic d) {
-    return (__umulhi(n, d.m) + n) >> d.s;
-}
-
 // Offsets (in cells) from x to x-1, x+1, y-1, ... with periodic wrap.
 struct Nbr {
     int32_t xm, xp, ym, yp, zm, zp;
@@ -107,26 +103,9 @@ __device__ __forceinline__ int32_t off_minus_rt(int i, const Nbr& n) {
     return o;
 }
 
+// Block of cells of this workgroup in the XCD-aware order of L.xcd_remap.
 __device__ __forceinline__ uint32_t block_id(const LatticeArgs& L) {
-    uint32_t b = blockIdx.x;
-    if (L.xcd_remap) {
-        // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.
-        // xcd_remap = 1: each XCD takes one contiguous range of blocks (best while
-        // the state sits in the last-level cache); K >= 2: the XCDs take turns on
-        // chunks of K consecutive blocks, so all of them stream through nearby
-        // addresses of each plane (better once the state is in HBM).  A last,
-        // incomplete round of 8 K blocks keeps the dispatch order.
-        const uint32_t G = gridDim.x, xcd = b & 7u, local = b >> 3;
-        const uint32_t K = (uint32_t)L.xcd_remap;
-        if (K >= 2) {
-            const uint32_t full = G / (8u * K) * (8u * K);
-            if (b < full) b = ((local / K) * 8u + xcd) * K + local % K;
-        } else {
-            const uint32_t per = G >> 3, rem = G & 7u;
-            b = xcd * per + (xcd < rem ? xcd : rem) + local;
-        }
-    }
-    return b;
+    return block_order(blockIdx.x, gridDim.x, L.xcd_remap);
 }
 
 // Plane addressing.  The 64-bit base of plane `slot` is uniform (SGPRs) and

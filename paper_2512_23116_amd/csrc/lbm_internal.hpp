@@ -11,6 +11,7 @@
 
 #include "../../include/lbm.h"
 #include "d3q19_mrt.hpp"
+#include "lbm_index.hpp"
 
 namespace lbm {
 
@@ -19,12 +20,6 @@ namespace lbm {
 //   AA_ODD : f_i(x) is at slot opp(i) of cell x-c_i (AA, odd step count)
 //   AB     : f_i(x) is at slot i of cell x-c_i in the current array
 enum Pattern : int { PAT_AA_EVEN = 0, PAT_AA_ODD = 1, PAT_AB = 2 };
-
-// Magic numbers for q = floor(n / d), n < 2^31: q = (umulhi(n, m) + n) >> s.
-struct DivMagic {
-    uint32_t m, s;
-};
-DivMagic make_div_magic(uint32_t d);
 
 // Everything a kernel needs about one lattice, passed by value.
 struct LatticeArgs {

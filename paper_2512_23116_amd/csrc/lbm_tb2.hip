@@ -67,12 +67,8 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     __shared__ R xbuf[TB_EX][4];        // x harmonics of the tile columns
 
     const LatticeArgs& L = A.L;
-    uint32_t b = blockIdx.x;
-    if (L.xcd_remap) {
-        const uint32_t G = gridDim.x, xcd = b & 7u, local = b >> 3;
-        const uint32_t per = G >> 3, rem = G & 7u;
-        b = xcd * per + (xcd < rem ? xcd : rem) + local;
-    }
+    // one contiguous range of tiles per XCD whenever a block order is asked for
+    const uint32_t b = block_order(blockIdx.x, gridDim.x, L.xcd_remap ? 1 : 0);
     const uint32_t tile_x = b % A.tiles_x;
     const uint32_t rest = b / A.tiles_x;
     const uint32_t tile_y = rest % A.tiles_y;

@@ -1,6 +1,7 @@
 """The plain-C example (paper_2512_23116_amd/examples/forced_hit.c) drives the
-C-ABI with no Python or torch in the process; its statistics must equal, bit for
-bit, those of the same run through the Python binding."""
+C-ABI with no Python or torch in the process (library-owned state, the null
+stream, 64-step graph replays); its statistics must equal, bit for bit, those of
+the same run through the Python binding."""
 import os
 import subprocess
 
@@ -32,12 +33,14 @@ def _parse(out):
 def test_c_example_matches_the_python_binding(precision, scheme):
     if not os.path.exists(EXAMPLE):
         pytest.fail("examples/forced_hit is not built (run __graft_entry__.build())")
-    N, steps, every, C, Re = 24, 60, 20, 0.13, 2.0e4
+    # 64 steps per lbm_step call: the example (library-owned state, null stream)
+    # replays its 64-step graph on the null stream, the binding on a torch stream
+    N, steps, every, C, Re = 24, 192, 64, 0.13, 2.0e4
     r = subprocess.run([EXAMPLE, str(N), str(steps), str(every), precision, scheme, str(C),
                         str(Re)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     snaps, spec = _parse(r.stdout)
-    assert [s["step"] for s in snaps] == [0, 20, 40, 60] and spec is not None
+    assert [s["step"] for s in snaps] == [0, 64, 128, 192] and spec is not None
 
     import numpy as np
     from paper_2512_23116_amd import lbm, params

@@ -58,18 +58,22 @@ def test_c1_taylor_green_fp64_one_step(lbm, orc, streaming):
     lat.close()
 
 
-@pytest.mark.parametrize("shape,smag,streaming", [
-    ((20, 17, 28), 0, "aa"),
-    ((20, 17, 28), 1, "ab"),
-    ((9, 33, 65), 0, "ab"),
+@pytest.mark.parametrize("shape,smag,streaming,C", [
+    ((20, 17, 28), 0, "aa", 0.13),
+    ((20, 17, 28), 1, "ab", 0.13),
+    ((9, 33, 65), 0, "ab", 0.13),
+    # C = 0: the DNS-MRT limit of the LES (Sec. 2.3), tau_e = tau0 everywhere
+    ((20, 17, 28), 0, "aa", 0.0),
+    ((9, 33, 65), 1, "ab", 0.0),
 ])
-def test_forced_noise_fp64_one_step(lbm, orc, shape, smag, streaming):
-    """Ragged non-cubic lattices, 16-mode solenoidal forcing, noise start, LES."""
+def test_forced_noise_fp64_one_step(lbm, orc, shape, smag, streaming, C):
+    """Ragged non-cubic lattices, 16-mode solenoidal forcing, noise start, LES
+    (and its C = 0 DNS limit)."""
     modes = forced_modes(F0=3e-5, seed=7)
-    lat = _lat(lbm, shape, 0.505, 0.13, modes, precision="fp64", streaming=streaming,
+    lat = _lat(lbm, shape, 0.505, C, modes, precision="fp64", streaming=streaming,
                smag_form=smag)
     lat.init(lbm.LBM_INIT_NOISE, 0.03, 42)
-    olat = orc.Lattice(shape, 0.505, 0.13, modes, smag_form=smag)
+    olat = orc.Lattice(shape, 0.505, C, modes, smag_form=smag)
     assert rel_err(lat.populations(), olat.init(I.KIND_NOISE, 0.03, 42)) < 1e-13
     for _ in range(4):
         fn = lat.populations()
@@ -110,12 +114,13 @@ def test_degenerate_and_tiny_lattices(lbm, orc, shape):
 # --------------------------------------------------------- FP32 parity ---
 
 @pytest.mark.parametrize("streaming", ["aa", "ab"])
-@pytest.mark.parametrize("case", ["tgv", "forced"])
+@pytest.mark.parametrize("case", ["tgv", "forced", "forced_dns"])
 def test_fp32_ten_steps(lbm, orc, streaming, case):
+    """FP32 storage over 10 steps; "forced_dns" is the forced case at C = 0."""
     shape = (32, 32, 32) if case == "tgv" else (30, 26, 34)
     modes = () if case == "tgv" else forced_modes(F0=3e-5, seed=11)
     kind, amp = (I.KIND_TGV3D, 0.02) if case == "tgv" else (I.KIND_NOISE, 0.02)
-    C = 0.1 if case == "tgv" else 0.13
+    C = {"tgv": 0.1, "forced": 0.13, "forced_dns": 0.0}[case]
     lat = _lat(lbm, shape, 0.51, C, modes, precision="fp32", streaming=streaming)
     lat.init(kind, amp, 5)
     olat = orc.Lattice(shape, 0.51, C, modes)

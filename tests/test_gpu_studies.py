@@ -18,6 +18,42 @@ def test_regime_study_small():
     assert math.isfinite(res["normalised_mean"]) and res["normalised_mean"] >= 1.0
 
 
+def test_regime_reproduces_the_papers_theta_statistics():
+    """The paper's LES regime (Sec. 4 setup, Sec. 5.1 result): 100^3, Re 2e4
+    (tau0 - 1/2 = 6.45e-4), C = 0.13 in the C_s^2 form, three-mode forcing,
+    Taylor-Green start, statistics of theta = tau_e - 1/2 over t/t0 in [200, 600]
+    (6e5 steps, 201 snapshots).  The paper prints a domain mean of about 1.34e-3
+    (normalised about 2.08), a 95th percentile at or below about 1.82e-3, a 5th
+    percentile above 1.0e-3 and no negative values.
+
+    Band: window means move by about 0.5 % between builds whose code generation
+    differs (the trajectory is chaotic; 201 snapshots sample it), and the paper
+    gives 3 significant figures (+-0.4 %), so the mean and the normalised mean
+    must lie within 2 % (4 x the scatter).  The percentiles are read off the
+    paper's envelope plot with an approximate sign ("below about 1.82e-3",
+    "above 1.0e-3", the latter to 2 figures, +-5 %): p95 <= 1.03 x 1.82e-3,
+    p5 >= 0.95 x 1.0e-3.  Every snapshot's minimum must be positive, and the
+    largest value stays of the order of the rare peaks the paper reports (global
+    maximum about 3.68e-3; one trajectory's extreme is not reproducible, so the
+    bound is 1.5 x that)."""
+    from paper_2512_23116_amd.studies import regime
+    res = regime.run(smag_form=1, C=0.13, t_start=200, t_end=600, every=2000,
+                     log=lambda m: print(m, flush=True))
+    w = res["window_mean"]
+    print({k: w[k] for k in ("mean", "p5", "p50", "p95", "p99", "min", "max")},
+          "normalised", res["normalised_mean"], flush=True)
+    assert res["setup"]["snapshots"] == 201
+    assert abs(w["mean"] / 1.34e-3 - 1.0) <= 0.02
+    assert abs(res["normalised_mean"] / 2.08 - 1.0) <= 0.02
+    assert w["p95"] <= 1.03 * 1.82e-3
+    assert w["p5"] >= 0.95 * 1.0e-3
+    assert w["min"] > 0.0 and w["max"] < 1.5 * 3.68e-3
+    # the device histogram pools the same cells: its percentiles agree with the
+    # snapshot-averaged ones to the bin width (1e-5) and the spread between snapshots
+    hp = res["histogram"]["pooled_percentiles"]
+    assert abs(hp["p50"] - w["p50"]) <= 2e-5 and abs(hp["p95"] - w["p95"]) <= 3e-5
+
+
 def test_precision_study_small():
     from paper_2512_23116_amd.studies import precision
     res = precision.study(32, 40, "fp64", ["fp32", "fp16"], n_snaps=2, log=lambda m: None)
