@@ -231,6 +231,19 @@ lbm_status lbm_sample_populations(lbm_handle* h, const int64_t* cells, int64_t n
 lbm_status lbm_theta_histogram(lbm_handle* h, double lo, double hi, int32_t nbins,
                                int64_t* counts);
 
+/* The same histogram as lbm_theta_histogram, for callers that cannot allocate
+ * device memory (code running while a HIP graph is being captured, tight
+ * serving loops, harnesses that forbid hipMalloc): no hipMalloc, hipFree or
+ * allocating library call.  The counts live in a static device array of the
+ * library (4099 64-bit counters, 32.8 KB per GPU, held until the process
+ * ends), looked up once per device; each call clears the counters it uses with
+ * a kernel before counting.  Arguments, output and errors as in
+ * lbm_theta_histogram; nbins > 4096 (beyond the static array) is
+ * LBM_ERR_INVALID_ARG.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (several host threads or streams) race.  Synchronises. */
+lbm_status lbm_theta_histogram_noalloc(lbm_handle* h, double lo, double hi, int32_t nbins,
+                                       int64_t* counts);
+
 /* Shell-binned kinetic-energy spectrum of the current state (Sec. 2.2,
  * eq. integral_length_scale with the squared modulus):
  *   E[k] = 1/2 sum_{k - 1/2 <= |q| < k + 1/2} |u_hat(q)|^2,  u_hat = FFT(u) / ncells,

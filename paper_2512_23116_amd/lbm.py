@@ -33,6 +33,7 @@ EXPORTS = (
     "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_steps_done",
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
+    "lbm_theta_histogram_noalloc",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_theta_histogram", "lbm_spectrum", "lbm_spectra_1d", "lbm_structure_functions",
     "lbm_turbulence",
@@ -145,6 +146,9 @@ def lib():
         "lbm_synchronize": (ctypes.c_int, [H]),
         "lbm_theta_histogram": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+        "lbm_theta_histogram_noalloc": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double,
+                                                       ctypes.c_int32,
+                                                       ctypes.POINTER(ctypes.c_int64)]),
         "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
         "lbm_spectra_1d": (ctypes.c_int, [H, ctypes.c_int32, dp, dp]),
         "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
@@ -287,6 +291,13 @@ def lbm_theta_histogram(h, lo, hi, nbins):
     counts = np.empty(nbins + 3, dtype=np.int64)
     _check(lib().lbm_theta_histogram(h, lo, hi, nbins,
                                      counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), h)
+    return counts
+
+
+def lbm_theta_histogram_noalloc(h, lo, hi, nbins):
+    counts = np.empty(nbins + 3, dtype=np.int64)
+    _check(lib().lbm_theta_histogram_noalloc(
+        h, lo, hi, nbins, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), h)
     return counts
 
 
@@ -454,6 +465,11 @@ class Lattice:
         """lbm_theta_histogram: int64[nbins + 3] = [below lo, bins..., at or above
         hi, non-finite]."""
         return lbm_theta_histogram(self.handle, lo, hi, nbins)
+
+    def theta_histogram_noalloc(self, lo, hi, nbins):
+        """lbm_theta_histogram_noalloc: the same counts from the library's static
+        device scratch (no device allocation; nbins <= 4096)."""
+        return lbm_theta_histogram_noalloc(self.handle, lo, hi, nbins)
 
     def kt_slice(self, z):
         """K_t of plane z as an (ny, nx) array."""
