@@ -3,24 +3,34 @@
 
 Prints ONE JSON line.  The headline workload is forced-HIT LES on a 100^3
 periodic lattice in FP32 with in-place AA streaming (Re = 2e4 at U0 = 0.043,
-C_s = 0.1 in nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with seeded phases, 1e-3 noise start,
-on-device K_t statistics, K_t map and energy spectrum every 500 steps).  A
-"step" is one lattice time step: the fused stream-and-collide kernel over
-every cell.  ``value`` is MLUPS
-(million lattice-cell updates per second) over the timed steps, with the
-state resident in HBM.
+C_s = 0.1 in nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with
+seeded phases, 1e-3 noise start) with its diagnostics every 500 lattice steps:
+the K_t / theta statistics, the K_t map of the mid-z plane (copied to the host)
+and the energy spectrum E(k), k <= N/2.
+
+A bench "step" is one pass of the whole hot path over the workload: one
+snapshot interval, i.e. 500 lattice time steps (one replay of a captured graph
+of 500 fused stream-and-collide launches) followed by that interval's
+diagnostics.  --steps K intervals are timed per repeat, --repeats R repeats
+(default 5), each bracketed by a device synchronisation; ``value`` is the
+median over the repeats of MLUPS (million lattice-cell updates per second, the
+diagnostics included), with the state resident in HBM.  The default K = 40 is
+the workload's 20 000 lattice steps.
 
 Beside it the same line carries: the roofline of the step kernel (algorithmic
-bytes 2 * 19 * 4 per cell update over its average launch time, from HIP events
-on the kernel's stream), the 800^3 FP32 runs (AA, A/B, A/B with two steps per
-pass), the 800^3 FP16 / BF16 storage runs (and FP16 with two steps per pass)
-with their K_t-statistics and spectral errors against the FP32 run, the batched-serving run (p50/p99
-completion latency and aggregate MLUPS), and the FP64 C oracle timed on the
-host cores on a bounded sample.
+bytes 2 * 19 * 4 per cell update over its mean launch time, from HIP events
+around the graph replays on the kernel's stream, next to the mean the committed
+rocprofv3 trace records and a same-size device copy for the cache-resident
+100^3 state), the 800^3 FP32 runs (AA, A/B, A/B with two steps per pass), the
+800^3 FP16 / BF16 storage runs (and FP16 with two steps per pass) with their
+K_t-statistics and spectral errors against the FP32 run, the batched-serving run
+(p50/p99 completion latency and aggregate MLUPS), and the FP64 C oracle timed
+on the host cores on a bounded sample.
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -36,11 +46,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def counter_traffic(workload_key, family="k_step"):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+TRAFFIC_TABLE = "hbm_traffic_step_kernels_forced_hit_100_800.txt"
+DURATION_TABLE = "durations_step_kernels_forced_hit_100_800.txt"
+
+
+def _profile_row(table, workload_key, family):
+    """The row of a committed per-lattice profile table for this lattice, if it was
     taken on the current sources of that kernel (else None)."""
     from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_forced_hit_100_800.txt")
+    path = os.path.join(ROOT, "profiles", table)
     if not os.path.exists(path):
         return None
     sha = kernel_source_sha(family)
@@ -48,8 +62,123 @@ def counter_traffic(workload_key, family="k_step"):
         parts = line.split()
         if len(parts) >= 5 and not line.startswith("#") and parts[0] == workload_key \
                 and parts[1] == sha:
-            return float(parts[2]) + float(parts[3])
+            return parts
     return None
+
+
+def counter_traffic(workload_key, family="k_step"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current sources of that kernel (else None)."""
+    parts = _profile_row(TRAFFIC_TABLE, workload_key, family)
+    return None if parts is None else float(parts[2]) + float(parts[3])
+
+
+def profile_launch_us(workload_key, family="k_step"):
+    """Mean duration of one step launch in the committed rocprofv3 kernel trace of
+    this command, if it was taken on the current kernel sources (else None)."""
+    parts = _profile_row(DURATION_TABLE, workload_key, family)
+    return None if parts is None else float(parts[2])
+
+
+def device_copy_rate(nbytes, reps=200):
+    """GB/s of a device-to-device copy of `nbytes` (read nbytes + write nbytes) on
+    nonzero data, timed with HIP events over `reps` copies: the bandwidth a
+    streaming kernel gets on a working set of that size (for 2 x 76 MB it stays
+    in the 256 MB last-level cache)."""
+    import torch
+    n = nbytes // 4
+    x = torch.rand(n, device="cuda") + 1.0
+    y = torch.empty_like(x)
+    for _ in range(20):
+        y.copy_(x)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 * reps / sec / 1e9
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in out.splitlines():
+        if line.lower().startswith("model name"):
+            return line.split(":", 1)[1].strip()
+    return None
+
+
+def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeats, interval):
+    """The headline workload: `repeats` timed runs of `intervals` snapshot
+    intervals each.  One interval = `interval` lattice steps (one graph replay)
+    and then the K_t statistics, the K_t map of the mid-z plane and the spectrum
+    E(k <= N/2) of the state reached.  The `warmup` intervals before the first
+    repeat capture the graph and create the FFT plan and the analysis buffers."""
+    import torch
+    stream = torch.cuda.Stream()
+    cfg = params.forced_hit(N)
+    spg = interval if interval % 4 == 0 and interval <= 1024 else 64
+    lat = lbm.Lattice((N, N, N), cfg["tau0"], cfg["C"], cfg["modes"], precision=precision,
+                      streaming=streaming, smag_form=cfg["smag_form"], steps_per_graph=spg,
+                      stream=stream)
+    lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
+    kmax, zmid = N // 2, N // 2
+
+    def snapshot():
+        return lat.stats(), lat.kt_slice(zmid), lat.spectrum(kmax)
+
+    for _ in range(warmup):
+        lat.step(interval)
+        snapshot()
+    lat.sync()
+    torch.cuda.synchronize()
+    reps, last = [], None
+    for _ in range(repeats):
+        events = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(intervals):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(interval)
+            e1.record(stream)
+            events.append((e0, e1))
+            last = snapshot()
+        lat.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
+        cells = N ** 3 * intervals * interval
+        reps.append(dict(wall_s=wall, mlups=cells / wall / 1e6,
+                         ms_per_step=wall / intervals * 1e3,
+                         avg_launch_us=kern_s / (intervals * interval) * 1e6))
+    st, sl, E = last
+    steps_done = lat.steps
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    order = sorted(range(repeats), key=lambda i: reps[i]["mlups"])
+    med = reps[order[repeats // 2]]
+    bytes_per_launch = 2 * 19 * BYTES[precision] * N ** 3
+    avg_us = statistics.median(r["avg_launch_us"] for r in reps)
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    return dict(N=N, median=med, repeats=reps, avg_launch_us=avg_us, tau0=cfg["tau0"],
+                spg=spg, steps_done=steps_done,
+                roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=achieved / PEAK_HBM_GBS, bytes_per_launch=bytes_per_launch),
+                kt=dict(mean=st["kt_mean"], var=st["kt_var"], flat=st["kt_flat"],
+                        theta_mean=st["theta_mean"], step=st["steps"]),
+                kt_map_mean=float(sl.mean()), spectrum_last=[float(v) for v in E[:26]])
 
 
 def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64, tb=0,
@@ -138,7 +267,8 @@ def cpu_baseline(N, target_s=12.0):
     dt = time.perf_counter() - t
     return dict(value=N ** 3 * n / dt / 1e6, unit="MLUPS", cores=ref_c.num_threads(),
                 kind="oracle",
-                sample=f"{N}^3 forced HIT, {n} steps of the plain C FP64 oracle (OpenMP)")
+                sample=f"{N}^3 forced HIT, {n} steps of the plain C FP64 oracle (OpenMP)",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
 def precision_errors(run, ref, N):
@@ -177,19 +307,28 @@ def run_serving(n_req, steps, seed=2024):
     mean_updates = sum(r.cells * r.steps for r in reqs) / len(reqs)
     rate = 0.8 * closed["busy_mlups"] * 1e6 / mean_updates
     log(f"serving closed batch: {closed['busy_mlups']:.0f} MLUPS busy, "
+        f"{closed['aggregate_mlups']:.0f} aggregate, busy {closed['busy_frac']:.3f}, "
         f"{closed['wall_s']:.1f} s; Poisson rate {rate:.2f}/s")
     reqs = serving.make_requests(n_req, seed=seed, steps=steps, rate=rate)
     eng = serving.GpuEngine(max_slots=16, steps_per_graph=64)
     res = serving.serve(reqs, eng, max_slots=16, hbm_budget=80e9)
     eng.close()
     return dict(requests=n_req, steps_each=steps, arrival_rate_per_s=rate,
+                offered_mlups=rate * mean_updates / 1e6,
                 p50_s=res["p50_s"], p99_s=res["p99_s"],
                 wait_p50_s=res["wait_p50_s"], wait_p99_s=res["wait_p99_s"],
                 service_p50_s=res["service_p50_s"], service_p99_s=res["service_p99_s"],
                 aggregate_mlups=res["aggregate_mlups"],
-                busy_mlups=res["busy_mlups"], busy_frac=res["busy_frac"], failed=res["failed"],
-                capacity_mlups=closed["busy_mlups"], slots=16, hbm_budget_gb=80,
-                group_mb=serving.GROUP_BYTES >> 20)
+                busy_mlups=res["busy_mlups"], busy_frac=res["busy_frac"],
+                busy_frac_when_work=res["busy_frac_when_work"], failed=res["failed"],
+                capacity_mlups=closed["busy_mlups"],
+                closed_batch={"wall_s": closed["wall_s"],
+                              "aggregate_mlups": closed["aggregate_mlups"],
+                              "busy_frac": closed["busy_frac"],
+                              "busy_frac_when_work": closed["busy_frac_when_work"]},
+                slots=16, hbm_budget_gb=80, group_mb=serving.GROUP_BYTES >> 20,
+                note="busy = GPU time of the batched calls (HIP events); busy_frac_when_work "
+                     "= busy / host time while a request was waiting, active or in flight")
 
 
 def profile_run(lbm, params, args):
@@ -221,13 +360,18 @@ def profile_run(lbm, params, args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=40,
+                    help="timed bench steps per repeat; one bench step = one snapshot interval "
+                         "(--diag-every lattice steps and their diagnostics)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed snapshot intervals")
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--N", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
     ap.add_argument("--streaming", default="aa", choices=["aa", "ab"])
-    ap.add_argument("--diag-every", type=int, default=500)
-    ap.add_argument("--steps-per-graph", type=int, default=64)
+    ap.add_argument("--diag-every", type=int, default=500,
+                    help="lattice steps per snapshot interval (one captured graph)")
+    ap.add_argument("--steps-per-graph", type=int, default=500,
+                    help="graph length of the 800^3 runs")
     ap.add_argument("--large-N", type=int, default=800)
     ap.add_argument("--large-steps", type=int, default=2000)
     ap.add_argument("--serving-requests", type=int, default=64)
@@ -259,13 +403,24 @@ def main():
         profile_run(lbm, params, args)
         return
 
-    log(f"main: {args.N}^3 {args.precision} {args.streaming}, {args.steps} steps")
-    main_run = run_lattice(lbm, params, args.N, args.precision, args.streaming, args.steps,
-                           args.warmup, args.diag_every, args.steps_per_graph, maps=True)
-    log(f"main: {main_run['mlups']:.0f} MLUPS, {main_run['avg_launch_us']:.1f} us/launch, "
-        f"{main_run['roofline']['frac']:.3f} of HBM peak")
+    if args.steps < 1 or args.repeats < 1 or args.warmup < 0:
+        print("--steps and --repeats must be >= 1, --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+    log(f"main: {args.N}^3 {args.precision} {args.streaming}, {args.repeats} x {args.steps} "
+        f"intervals of {args.diag_every} steps after {args.warmup} warm-up intervals")
+    main_run = run_workload(lbm, params, args.N, args.precision, args.streaming, args.steps,
+                            args.warmup, args.repeats, args.diag_every)
+    med = main_run["median"]
+    log(f"main: {med['mlups']:.0f} MLUPS (median of {args.repeats}; "
+        f"{min(r['mlups'] for r in main_run['repeats']):.0f}-"
+        f"{max(r['mlups'] for r in main_run['repeats']):.0f}), "
+        f"{main_run['avg_launch_us']:.2f} us/launch, {main_run['roofline']['frac']:.3f} of HBM peak")
     key = f"{args.N}_{args.precision}_{args.streaming}"
     main_run["roofline"]["traffic"] = counter_traffic(key)
+    # the state and the copy of the same bytes: cache-resident below 256 MB
+    state_bytes = 19 * BYTES[args.precision] * args.N ** 3
+    copy_gbs = device_copy_rate(state_bytes)
+    log(f"main: device copy of {state_bytes / 1e6:.0f} MB at {copy_gbs:.0f} GB/s")
 
     large = None
     if not args.no_large:
@@ -336,7 +491,9 @@ def main():
         log(f"serving: {args.serving_requests} requests x {args.serving_steps} steps")
         serving = run_serving(args.serving_requests, args.serving_steps)
         log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s, "
-            f"{serving['aggregate_mlups']:.0f} MLUPS aggregate")
+            f"{serving['aggregate_mlups']:.0f} MLUPS aggregate of "
+            f"{serving['offered_mlups']:.0f} offered, busy {serving['busy_frac']:.3f} "
+            f"({serving['busy_frac_when_work']:.3f} while work was present)")
 
     cpu = None
     if not args.no_cpu:
@@ -345,14 +502,19 @@ def main():
         log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
 
     r = main_run["roofline"]
+    mlups_all = [round(x["mlups"], 1) for x in main_run["repeats"]]
     out = {
         "metric": METRIC,
-        "value": round(main_run["mlups"], 1),
+        "value": round(med["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_run["ms_per_step"], 6),
+        "ms_per_step": round(med["ms_per_step"], 4),
+        "repeats": args.repeats,
+        "value_repeats": mlups_all,
+        "lattice_steps_per_step": args.diag_every,
+        "ms_per_lattice_step": round(med["ms_per_step"] / args.diag_every, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -362,21 +524,36 @@ def main():
             "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C_s=0.1 "
                          f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
                          f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
-                         f"forcing, 1e-3 noise start; every {args.diag_every} steps K_t "
-                         "statistics, K_t map (mid-z plane to host) and energy spectrum, "
-                         "all inside the timed region"),
+                         f"forcing, 1e-3 noise start; one step = {args.diag_every} lattice "
+                         f"steps (one graph replay) + K_t/theta statistics + K_t map of the "
+                         f"mid-z plane to host + energy spectrum E(k<={args.N // 2}); "
+                         f"{args.steps} steps ({args.steps * args.diag_every} lattice steps, "
+                         f"{args.steps} snapshots of each diagnostic) timed per repeat, "
+                         f"median of {args.repeats} repeats after {args.warmup} warm-up steps"),
             "N": args.N, "precision": args.precision, "streaming": args.streaming,
-            "steps_per_graph": args.steps_per_graph, "parallelism": "single GPU",
+            "steps_per_graph": main_run["spg"], "parallelism": "single GPU",
         },
         "roofline": {"bound": r["bound"], "achieved": round(r["achieved"], 1), "peak": r["peak"],
                      "unit": r["unit"], "frac": round(r["frac"], 4), "traffic": r["traffic"],
                      "kernel": f"k_step {args.precision} {args.streaming}",
                      "bytes_per_launch": r["bytes_per_launch"],
-                     "avg_launch_us": round(main_run["avg_launch_us"], 3)},
+                     "avg_launch_us": round(main_run["avg_launch_us"], 3),
+                     "avg_launch_source": "HIP events around the graph replays of the timed "
+                                          "repeats (median), divided by the launches",
+                     "profile_avg_launch_us": profile_launch_us(key),
+                     "cache_resident": state_bytes < (256 << 20),
+                     "device_copy_same_bytes": {
+                         "GBs": round(copy_gbs, 1),
+                         "frac": round(r["achieved"] / copy_gbs, 4),
+                         "note": "torch device copy of the state's size on nonzero data, "
+                                 "the streaming rate of this working set"}},
         "cpu_baseline": cpu,
         "kt": main_run["kt"],
-        "diagnostics": {"every": args.diag_every, "kt_stats": main_run["kt"]["n_snapshots"],
-                        "kt_maps": main_run["n_maps"], "spectra": main_run["n_spectra"],
+        "diagnostics": {"every": args.diag_every,
+                        "per_repeat": {"kt_stats": args.steps, "kt_maps": args.steps,
+                                       "spectra": args.steps},
+                        "lattice_steps_done": main_run["steps_done"],
+                        "kt_map_mean_last": main_run["kt_map_mean"],
                         "spectrum_last_k0_25": main_run["spectrum_last"]},
     }
     if large:
@@ -386,7 +563,10 @@ def main():
                         "ms_per_step": round(large["ms_per_step"], 4),
                         "roofline": {"bound": "hbm", "achieved": round(lr["achieved"], 1),
                                      "peak": lr["peak"], "unit": "GB/s",
-                                     "frac": round(lr["frac"], 4), "traffic": lr["traffic"]},
+                                     "frac": round(lr["frac"], 4), "traffic": lr["traffic"],
+                                     "avg_launch_us": round(large["avg_launch_us"], 2),
+                                     "profile_avg_launch_us":
+                                         profile_launch_us(f"{args.large_N}_fp32_aa")},
                         "kt": large["kt"], "kt_series": large["kt_series"]}
     if large_ab:
         lr = large_ab["roofline"]

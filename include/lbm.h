@@ -329,6 +329,16 @@ lbm_status lbm_load_state(lbm_handle* h, const void* host, size_t bytes, int64_t
 /* Wait for all work issued on the handle's stream; DEVICE on kernel errors. */
 lbm_status lbm_synchronize(lbm_handle* h);
 
+/* Move the handle to another HIP stream (hipStream_t, or NULL for the null
+ * stream): every later call on the handle, its graph replays included,
+ * enqueues there.  Nothing is synchronised and nothing is launched: the caller
+ * orders the new stream after the work still pending on the old one (for
+ * instance with an event), as it would for any two streams.  Used by the
+ * serving loop to set a lattice up and to read its final statistics on a side
+ * stream while batched steps run on the main one.  Always LBM_OK for a
+ * non-NULL handle. */
+lbm_status lbm_set_stream(lbm_handle* h, void* hip_stream);
+
 int64_t lbm_steps_done(const lbm_handle* h);
 int64_t lbm_num_cells(const lbm_handle* h);
 
@@ -354,7 +364,9 @@ const char* lbm_last_error(const lbm_handle* h);
  *   or 0 for plain launches; hip_stream as in lbm_config.
  * lbm_batch_step: advance hs[i] by steps[i] (0 <= steps[i] <= steps_per_graph,
  *   or any >= 0 when steps_per_graph is 0) for i < n <= max_slots, handles
- *   distinct.  Asynchronous; INVALID_ARG (nothing launched) on a bad argument.
+ *   distinct.  One graph replay when max steps[i] equals steps_per_graph, else
+ *   max steps[i] plain launches.  Asynchronous; INVALID_ARG (nothing launched)
+ *   on a bad argument.
  * lbm_batch_destroy: NULL allowed; synchronises the stream first. */
 lbm_status lbm_batch_create(int32_t max_slots, int32_t steps_per_graph, void* hip_stream,
                             lbm_batch** out);

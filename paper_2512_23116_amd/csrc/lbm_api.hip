@@ -608,6 +608,13 @@ lbm_status lbm_synchronize(lbm_handle* h) {
     return sync(h);
 }
 
+lbm_status lbm_set_stream(lbm_handle* h, void* hip_stream) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)hip_stream;
+    h->cfg.hip_stream = hip_stream;
+    return LBM_OK;
+}
+
 int64_t lbm_steps_done(const lbm_handle* h) { return h ? h->steps : -1; }
 
 int64_t lbm_num_cells(const lbm_handle* h) { return h ? (int64_t)h->args.ncell : -1; }

@@ -214,7 +214,9 @@ lbm_status lbm_batch_step(lbm_batch* b, lbm_handle* const* hs, const int32_t* st
     BCHK(b, hipMemcpyAsync(b->d_table, t, bytes, hipMemcpyHostToDevice, b->stream));
     BCHK(b, hipEventRecord(b->copied, b->stream));
 
-    if (b->G > 0 && 2 * kmax > b->G) {
+    // the graph only when every one of its launches has work: a shorter call
+    // launches exactly kmax kernels instead of replaying empty ones
+    if (b->G > 0 && kmax == b->G) {
         if (!b->gexec) {
             lbm_status st = capture(b);
             if (st != LBM_OK) return st;

@@ -204,7 +204,6 @@ __device__ __forceinline__ void force_at(const LatticeArgs& L, const CellPos& p,
 // NT: bit 0 = non-temporal loads, bit 1 = non-temporal stores.
 template <class Cd, int PAT, int NT = 0>
 __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
-    using T = typename Cd::T;
     using R = typename Cd::R;
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);

@@ -50,7 +50,6 @@ __device__ __forceinline__ double wave_max(double v) {
 
 template <class Cd, int PAT>
 __global__ __launch_bounds__(256) void k_diag(LatticeArgs L, double* partials) {
-    using T = typename Cd::T;
     using R = typename Cd::R;
     double acc[kDiagUsed];
 #pragma unroll
@@ -138,7 +137,6 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* partials, int 
 // ------------------------------------------------------ observation ---
 template <class Cd, int PAT>
 __global__ __launch_bounds__(256) void k_moments(LatticeArgs L, double* rho, double* u) {
-    using T = typename Cd::T;
     using R = typename Cd::R;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     if (cell >= L.ncell) return;

@@ -30,7 +30,8 @@ STREAMING = {"aa": LBM_STREAM_AA, "ab": LBM_STREAM_AB}
 EXPORTS = (
     "lbm_config_default", "lbm_required_bytes", "lbm_create", "lbm_init_seeded", "lbm_step",
     "lbm_moments", "lbm_kt_stats", "lbm_kt_field", "lbm_kt_slice", "lbm_get_populations",
-    "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_steps_done",
+    "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_set_stream",
+    "lbm_steps_done",
     "lbm_num_cells", "lbm_destroy", "lbm_status_string", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_destroy",
     "lbm_theta_histogram_noalloc",
@@ -144,6 +145,7 @@ def lib():
         "lbm_sample_populations": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int64),
                                                   ctypes.c_int64, dp]),
         "lbm_synchronize": (ctypes.c_int, [H]),
+        "lbm_set_stream": (ctypes.c_int, [H, ctypes.c_void_p]),
         "lbm_theta_histogram": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
         "lbm_theta_histogram_noalloc": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_double,
@@ -333,6 +335,10 @@ def lbm_synchronize(h):
     _check(lib().lbm_synchronize(h), h)
 
 
+def lbm_set_stream(h, stream_ptr):
+    _check(lib().lbm_set_stream(h, stream_ptr), h)
+
+
 def lbm_steps_done(h):
     return int(lib().lbm_steps_done(h))
 
@@ -432,6 +438,12 @@ class Lattice:
     def sync(self):
         """lbm_synchronize: wait for the lattice's stream."""
         lbm_synchronize(self.handle)
+
+    def set_stream(self, stream):
+        """lbm_set_stream: later calls run on `stream` (a torch.cuda.Stream).  The
+        caller orders it after the work pending on the old stream."""
+        lbm_set_stream(self.handle, stream.cuda_stream)
+        self.stream = stream
 
     @property
     def steps(self):

@@ -15,6 +15,9 @@ calibrated bytes per step launch are compared with the algorithmic 2*19*b*N^3.
 With ``--traffic-out`` one line per lattice is appended for bench.py:
 ``<N>_<precision>_<streaming>[_tb2] <kernel-source sha> <fetch bytes> <write bytes>``,
 the sha taken over the sources that kernel is compiled from (KERNEL_SOURCES).
+With ``--durations-out`` the trace's mean duration per step launch is written
+the same way (``<key> <sha> <mean us> <launches> <family>``), so that bench.py can
+print the profile's figure beside its own live HIP-event mean.
 """
 import argparse
 import collections
@@ -30,7 +33,7 @@ COPY_BYTES = 1 << 30
 
 # Sources each step kernel is compiled from: its counters stay valid while these
 # files are unchanged.
-_COMMON = ("d3q19_mrt.hpp", "lbm_device.hpp", "lbm_internal.hpp")
+_COMMON = ("d3q19_mrt.hpp", "lbm_device.hpp", "lbm_internal.hpp", "lbm_index.hpp")
 KERNEL_SOURCES = {
     "k_step": ("lbm_kernels.hip",) + _COMMON,
     "k_step_tb2": ("lbm_tb2.hip",) + _COMMON,
@@ -127,6 +130,7 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--streaming", default="aa")
     ap.add_argument("--traffic-out")
+    ap.add_argument("--durations-out")
     ap.add_argument("--tb2-n", type=int, default=800,
                     help="lattice edge of the two-step kernel launches in the counter runs")
     a = ap.parse_args()
@@ -139,8 +143,26 @@ def main():
         print("\nkernel trace (durations in us; grid = threads launched)")
         print(f"{'kernel':58s} {'grid':>11s} {'calls':>6s} {'mean':>10s} {'median':>10s} "
               f"{'min':>10s} {'max':>10s}")
-        for k, g, n, mean, med, lo, hi in trace_table(a.trace):
+        table = trace_table(a.trace)
+        for k, g, n, mean, med, lo, hi in table:
             print(f"{k[:58]:58s} {g:11d} {n:6d} {mean:10.2f} {med:10.2f} {lo:10.2f} {hi:10.2f}")
+        per_key = collections.defaultdict(lambda: [0.0, 0, ""])
+        for k, g, n, mean, med, lo, hi in table:
+            lk = lattice_key(k, g, a.precision, a.tb2_n)
+            if lk is None:
+                continue
+            fam, key = lk
+            acc = per_key[key]
+            acc[0] += mean * n
+            acc[1] += n
+            acc[2] = fam
+        print("\nmean duration per step launch (all launches of the lattice, even and odd)")
+        for key, (tot, n, fam) in sorted(per_key.items()):
+            print(f"{key:>16s} {fam:>10s} {n:6d} launches {tot / n:10.2f} us")
+        if a.durations_out:
+            write_table(a.durations_out, {k: (v[0] / v[1], v[1], v[2]) for k, v in per_key.items()},
+                        lambda key, val: f"{key} {kernel_source_sha(val[2])} {val[0]:.3f} "
+                                         f"{val[1]} {val[2]}\n", fam_col=4)
     if a.fetch and a.write:
         fb = counters(a.fetch, "FETCH_SIZE")
         wb = counters(a.write, "WRITE_SIZE")
@@ -172,10 +194,10 @@ def main():
             write_traffic(a.traffic_out, per_key)
 
 
-def write_traffic(path, per_key):
-    """Rewrite the traffic table: its comment lines, the earlier entries that were
-    taken on the current sources of their kernel and not measured again now, then
-    the new entries.  Entries of older sources are dropped."""
+def write_table(path, per_key, fmt, fam_col):
+    """Rewrite a per-lattice table: its comment lines, the earlier entries that
+    were taken on the current sources of their kernel and not measured again now,
+    then the new entries.  Entries of older sources are dropped."""
     current = {fam: kernel_source_sha(fam) for fam in KERNEL_SOURCES}
     head, keep = [], []
     if os.path.exists(path):
@@ -184,12 +206,19 @@ def write_traffic(path, per_key):
                 head.append(ln)
                 continue
             parts = ln.split()
-            if len(parts) >= 5 and parts[0] not in per_key and current.get(parts[4]) == parts[1]:
+            if len(parts) > fam_col and parts[0] not in per_key \
+                    and current.get(parts[fam_col]) == parts[1]:
                 keep.append(ln)
     with open(path, "w") as fh:
         fh.writelines(head + keep)
-        for key, (f, w, n, fam) in sorted(per_key.items()):
-            fh.write(f"{key} {current[fam]} {f / n:.6e} {w / n:.6e} {fam} mean over {n} kernels\n")
+        for key, val in sorted(per_key.items()):
+            fh.write(fmt(key, val))
+
+
+def write_traffic(path, per_key):
+    write_table(path, per_key,
+                lambda key, v: f"{key} {kernel_source_sha(v[3])} {v[0] / v[2]:.6e} "
+                               f"{v[1] / v[2]:.6e} {v[3]} mean over {v[2]} kernels\n", fam_col=4)
 
 
 if __name__ == "__main__":
