@@ -164,6 +164,7 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
                          avg_launch_us=kern_s / (intervals * interval) * 1e6))
     st, sl, E = last
     steps_done = lat.steps
+    ceil = pattern_ceiling(lat, stream, 200)
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -178,16 +179,44 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
                               frac=achieved / PEAK_HBM_GBS, bytes_per_launch=bytes_per_launch),
                 kt=dict(mean=st["kt_mean"], var=st["kt_var"], flat=st["kt_flat"],
                         theta_mean=st["theta_mean"], step=st["steps"]),
-                kt_map_mean=float(sl.mean()), spectrum_last=[float(v) for v in E[:26]])
+                kt_map_mean=float(sl.mean()), spectrum_last=[float(v) for v in E[:26]],
+                pattern=ceil)
+
+
+def launch_ms(stream, fn, n):
+    """Mean ms per launch of `fn(n)` (n plain launches) from HIP events on `stream`."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn(n)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def pattern_ceiling(lat, stream, n):
+    """The step's data movement alone against the step: `n` plain launches of free
+    streaming (lbm_stream_only: the same loads, stores, layout and block order, no
+    arithmetic) and `n` plain step launches, ms per launch.  Changes the state (taken
+    after the workload's last statistics)."""
+    lat.stream_only(2)
+    stream_ms = launch_ms(stream, lat.stream_only, n)
+    lat.step(2)
+    step_ms = launch_ms(stream, lat.step, n)
+    return dict(stream_only_ms=round(stream_ms, 5), step_plain_ms=round(step_ms, 5),
+                step_over_stream=round(step_ms / stream_ms, 4),
+                note="plain launches, HIP events; stream_only = lbm_stream_only, the step's "
+                     "loads and stores with no collision")
 
 
 def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every, spg=64, tb=0,
-                maps=False, final_spectrum=0):
-    """Time `steps` steps; every `diag_every` steps take the K_t statistics (and with
-    `maps` also the K_t field, keeping its mid-z slice on the host, and the energy
-    spectrum): the diagnostics of the workload run inside the timed region.  With
+                final_spectrum=0, ceiling=0):
+    """Time `steps` steps; every `diag_every` steps take the K_t statistics: the
+    diagnostics of the workload run inside the timed region.  With
     `final_spectrum` = K the spectrum E(0..K) of the last state is taken after the
-    clock stops."""
+    clock stops, and with `ceiling` = n the data-movement ceiling of the step's
+    access pattern is measured after that (pattern_ceiling, n launches)."""
     import torch
     stream = torch.cuda.Stream()
     cfg = params.forced_hit(N)
@@ -196,13 +225,7 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
                       temporal_block=tb, stream=stream)
     lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
     stats = [lat.stats()] if warmup == 0 else []
-    kt_slices, spectra = [], []
     lat.step(warmup)
-    if maps:
-        # one-time set-up outside the timed region: the FFT plan and the analysis
-        # and staging buffers
-        lat.spectrum(N // 2)
-        lat.kt_slice(N // 2)
     lat.sync()
     events = []
     torch.cuda.synchronize()
@@ -219,15 +242,13 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
         done += n
         if diag_every and done % diag_every == 0:
             stats.append(lat.stats())
-            if maps:
-                kt_slices.append(lat.kt_slice(N // 2))
-                spectra.append(lat.spectrum(N // 2))
     lat.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
     final = lat.stats()
     spec_final = lat.spectrum(final_spectrum) if final_spectrum else None
+    ceil = pattern_ceiling(lat, stream, ceiling) if ceiling and tb == 0 else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -245,9 +266,7 @@ def run_lattice(lbm, params, N, precision, streaming, steps, warmup, diag_every,
                         theta_mean=final["theta_mean"], n_snapshots=len(stats)),
                 kt_series=[dict(step=st["steps"], mean=st["kt_mean"], var=st["kt_var"],
                                 flat=st["kt_flat"]) for st in stats],
-                n_maps=len(kt_slices), n_spectra=len(spectra),
-                spectrum_last=[float(v) for v in spectra[-1][:26]] if spectra else None,
-                spectrum_final=spec_final, tau0=cfg["tau0"])
+                spectrum_final=spec_final, tau0=cfg["tau0"], pattern=ceil)
 
 
 def cpu_baseline(N, target_s=12.0):
@@ -429,7 +448,12 @@ def main():
         # clocks are up from the main run; graph capture costs ~1 ms of the timed span)
         large = run_lattice(lbm, params, args.large_N, "fp32", "aa", args.large_steps, 0,
                             args.diag_every, args.steps_per_graph,
-                            final_spectrum=0 if args.no_precision else args.large_N // 4)
+                            final_spectrum=0 if args.no_precision else args.large_N // 4,
+                            ceiling=10)
+        large_copy_gbs = device_copy_rate(19 * 4 * args.large_N ** 3, reps=20)
+        log(f"large: device copy of the state's bytes at {large_copy_gbs:.0f} GB/s; step "
+            f"{large['pattern']['step_plain_ms']:.3f} ms vs free streaming "
+            f"{large['pattern']['stream_only_ms']:.3f} ms per launch")
         large["roofline"]["traffic"] = counter_traffic(f"{args.large_N}_fp32_aa")
         log(f"large: {large['mlups']:.0f} MLUPS, {large['roofline']['frac']:.3f} of HBM peak")
 
@@ -437,7 +461,7 @@ def main():
     if not args.no_large and not args.no_large_ab:
         log(f"large A/B: {args.large_N}^3 fp32 ab, {args.large_steps // 2} steps")
         large_ab = run_lattice(lbm, params, args.large_N, "fp32", "ab", args.large_steps // 2, 64,
-                               args.diag_every, args.steps_per_graph)
+                               args.diag_every, args.steps_per_graph, ceiling=10)
         log(f"large A/B: {large_ab['mlups']:.0f} MLUPS, {large_ab['roofline']['frac']:.3f} of HBM peak")
         log(f"large A/B two steps per pass: {args.large_N}^3 fp32, {args.large_steps} steps")
         large_tb2 = run_lattice(lbm, params, args.large_N, "fp32", "ab", args.large_steps, 64,
@@ -451,7 +475,7 @@ def main():
             log(f"precision: {args.large_N}^3 {prec} aa, {args.large_steps} steps")
             pr = run_lattice(lbm, params, args.large_N, prec, "aa", args.large_steps, 0,
                              args.diag_every, args.steps_per_graph,
-                             final_spectrum=args.large_N // 4)
+                             final_spectrum=args.large_N // 4, ceiling=10)
             rr = pr["roofline"]
             precision[prec] = {
                 "workload": (f"forced HIT LES {args.large_N}^3, populations stored as {prec} "
@@ -460,7 +484,8 @@ def main():
                 "ms_per_step": round(pr["ms_per_step"], 4),
                 "roofline": {"bound": "hbm", "achieved": round(rr["achieved"], 1),
                              "peak": rr["peak"], "unit": "GB/s", "frac": round(rr["frac"], 4),
-                             "traffic": counter_traffic(f"{args.large_N}_{prec}_aa")},
+                             "traffic": counter_traffic(f"{args.large_N}_{prec}_aa"),
+                             "pattern_ceiling": pr["pattern"]},
                 "vs_fp32": precision_errors(pr, large, args.large_N)}
             log(f"precision: {prec} {pr['mlups']:.0f} MLUPS, {rr['frac']:.3f} of HBM peak, "
                 f"K_t mean rel err {precision[prec]['vs_fp32']['kt_rel_err_max']['mean']:.2e}")
@@ -541,6 +566,7 @@ def main():
                      "avg_launch_source": "HIP events around the graph replays of the timed "
                                           "repeats (median), divided by the launches",
                      "profile_avg_launch_us": profile_launch_us(key),
+                     "pattern_ceiling": main_run["pattern"],
                      "cache_resident": state_bytes < (256 << 20),
                      "device_copy_same_bytes": {
                          "GBs": round(copy_gbs, 1),
@@ -566,7 +592,11 @@ def main():
                                      "frac": round(lr["frac"], 4), "traffic": lr["traffic"],
                                      "avg_launch_us": round(large["avg_launch_us"], 2),
                                      "profile_avg_launch_us":
-                                         profile_launch_us(f"{args.large_N}_fp32_aa")},
+                                         profile_launch_us(f"{args.large_N}_fp32_aa"),
+                                     "pattern_ceiling": large["pattern"],
+                                     "device_copy_same_bytes": {
+                                         "GBs": round(large_copy_gbs, 1),
+                                         "frac": round(lr["achieved"] / large_copy_gbs, 4)}},
                         "kt": large["kt"], "kt_series": large["kt_series"]}
     if large_ab:
         lr = large_ab["roofline"]
@@ -576,7 +606,8 @@ def main():
                            "roofline": {"bound": "hbm", "achieved": round(lr["achieved"], 1),
                                         "peak": lr["peak"], "unit": "GB/s",
                                         "frac": round(lr["frac"], 4),
-                                        "traffic": counter_traffic(f"{args.large_N}_fp32_ab")}}
+                                        "traffic": counter_traffic(f"{args.large_N}_fp32_ab"),
+                                        "pattern_ceiling": large_ab["pattern"]}}
     if large_tb2:
         lr = large_tb2["roofline"]
         # one launch = one pass = two time steps; its algorithmic bytes are one read

@@ -183,6 +183,15 @@ lbm_status lbm_init_seeded(lbm_handle* h, int32_t kind, double amplitude, uint64
  * Full graphs of steps_per_graph steps are replayed, the rest is launched. */
 lbm_status lbm_step(lbm_handle* h, int64_t n);
 
+/* Advance n >= 0 steps of free streaming: the left side of eq. mrt_dns_guo with
+ * the collision replaced by the identity (f(x + c_i, t + 1) = f(x, t), no force),
+ * i.e. every population moves one cell along its velocity, periodically.  It
+ * performs exactly the loads and stores of lbm_step (same access pattern,
+ * block order and state layout, no arithmetic), so its duration is the
+ * ceiling of the step's data movement; the state stays exact in every storage
+ * format.  Plain launches, asynchronous; counts as steps (lbm_steps_done). */
+lbm_status lbm_stream_only(lbm_handle* h, int64_t n);
+
 /* rho[c] and u[a * ncells + c] (a = x, y, z) of the current state, with the
  * half-force velocity of eq. guo_velocity.  Host arrays of ncells and
  * 3*ncells doubles; either may be NULL.  Synchronises. */

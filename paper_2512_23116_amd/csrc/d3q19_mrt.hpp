@@ -68,9 +68,18 @@ struct CellMacro {
 // Collide one cell in place.  g: deviation populations (pre-collision in,
 // post-collision out).  F: body force at the cell.  kFull = false computes
 // only the macroscopic quantities and tau_e (diagnostics) and leaves g as is.
-template <typename R, bool kFull>
+//
+// kScaled: g and F come in units of 1/sigma (sigma g, sigma F, with sigma = 1/is
+// a power of two: the 16-bit storage scale) and g leaves in the same units, so
+// the storage codec needs no multiplications.  Every moment, equilibrium and
+// relaxed moment is then exactly sigma times its unscaled value (power-of-two
+// scaling commutes with rounding); the four places that need unscaled values
+// (rho, 1/rho, |S| -> tau_e, the diagnostics' |S|^2 and delta rho) apply is, so
+// the result equals sigma times the unscaled collision's, bit for bit.  The
+// returned CellMacro is unscaled either way.
+template <typename R, bool kFull, bool kScaled = false>
 __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
-                                                const CollideConst<R>& k) {
+                                                const CollideConst<R>& k, R is = R(1)) {
     const R h = R(0.5);
     // pair sums (even rows) and differences (odd rows)
     const R p0 = g[0] + g[1], d0 = g[0] - g[1];
@@ -109,9 +118,11 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
     const R m17 = d4 - d3 + d5 + d6;
     const R m18 = d6 - d5 + d7 - d8;
 
-    // eq. guo_velocity: rho u = sum f c + F/2
-    const R rho = k.rho0 + m0;
-    const R inv_rho = fast_rcp(rho);
+    // eq. guo_velocity: rho u = sum f c + F/2 (rux.. and the products below carry
+    // the scale of g; u itself is unscaled)
+    const R drho = kScaled ? m0 * is : m0;
+    const R rho = k.rho0 + drho;
+    const R inv_rho = kScaled ? fast_rcp(rho) * is : fast_rcp(rho);
     const R rux = jx + h * Fx, ruy = jy + h * Fy, ruz = jz + h * Fz;
     const R ux = rux * inv_rho, uy = ruy * inv_rho, uz = ruz * inv_rho;
     const R xx = rux * ux, yy = ruy * uy, zz = ruz * uz;   // rho u_a u_a
@@ -136,7 +147,7 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
     const R S2 = R(2) * (Sxx * Sxx + Syy * Syy + Szz * Szz) +
                  R(4) * (Sxy * Sxy + Sxz * Sxz + Syz * Syz);
     // eq. les_viscosity: tau_e = 1/2 + 3 (nu0 + C Delta^2 |S|) = tau0 + 3 C |S|
-    R tau_t = k.c3 * fast_sqrt(S2);
+    R tau_t = (kScaled ? k.c3 * is : k.c3) * fast_sqrt(S2);
     if (k.self_consistent) {
         // (the empty asm keeps this a uniform branch instead of computing it
         // always and selecting, so the default mode pays nothing for it)
@@ -150,9 +161,10 @@ __device__ __forceinline__ CellMacro<R> collide(R (&g)[19], R Fx, R Fy, R Fz,
     const R tau_e = k.tau0 + tau_t;
     // |S|^2: S2 itself, or (|S_1| / tau_e)^2 in the self-consistent mode.  Only the
     // diagnostics read it; the step kernels drop it.
-    const R snorm2 = k.self_consistent ? S2 * fast_rcp(tau_e * tau_e) : S2;
+    const R S2u = kScaled ? S2 * (is * is) : S2;
+    const R snorm2 = k.self_consistent ? S2u * fast_rcp(tau_e * tau_e) : S2u;
 
-    CellMacro<R> out{m0, rho, ux, uy, uz, tau_t, snorm2};
+    CellMacro<R> out{drho, rho, ux, uy, uz, tau_t, snorm2};
     if constexpr (!kFull) {
         return out;
     } else {

@@ -404,6 +404,18 @@ lbm_status lbm_step(lbm_handle* h, int64_t n) {
     return LBM_OK;
 }
 
+lbm_status lbm_stream_only(lbm_handle* h, int64_t n) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (n < 0) return fail(h, LBM_ERR_INVALID_ARG, "n must be >= 0");
+    if (!h->initialized) return fail(h, LBM_ERR_STATE, "lbm_stream_only before lbm_init_seeded/lbm_set_populations");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e = launch_stream(h->cfg.precision, current_pattern(h), current_args(h), h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "streaming kernel");
+        advance(h);
+    }
+    return LBM_OK;
+}
+
 lbm_status lbm_moments(lbm_handle* h, double* rho, double* u) {
     if (!h) return LBM_ERR_INVALID_ARG;
     if (!h->initialized) return fail(h, LBM_ERR_STATE, "state not initialised");

@@ -29,6 +29,14 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
     return __builtin_bit_cast(uint16_t, h);
 }
 
+// Whether the one-step kernel collides on the stored scale (collide's kScaled),
+// so that the codec reduces to conversions: for BF16 (shift / convert plus a
+// multiply each way otherwise).  FP16 keeps the unscaled form: its decode and
+// encode already fold the scale into mixed-precision FMAs (v_fma_mix*), and
+// the scaled form measured 5 VALU instructions more per cell.
+template <class Cd>
+constexpr bool kScaledCodec = std::is_same_v<Cd, CdBF16>;
+
 template <class Cd>
 __device__ __forceinline__ typename Cd::R dec(typename Cd::T v, typename Cd::R inv_s) {
     if constexpr (std::is_same_v<Cd, CdF16>) return (float)v * inv_s;
@@ -207,11 +215,19 @@ __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
     using R = typename Cd::R;
     const CellPos p = decode(cell, L);
     const Nbr nb = make_nbr(p, L);
+    constexpr bool kS = kScaledCodec<Cd>;
     R g[19];
-    load_cell<Cd, PAT, (NT & 1) != 0>(PlaneTable{L.pa}, cell, nb, g, inv_scale_of<R>(L));
+    load_cell<Cd, PAT, (NT & 1) != 0>(PlaneTable{L.pa}, cell, nb, g,
+                                      kS ? R(1) : inv_scale_of<R>(L));
     R Fx, Fy, Fz;
     force_at<R>(L, p, Fx, Fy, Fz);
-    collide<R, true>(g, Fx, Fy, Fz, collide_const<R>(L));
+    if constexpr (kS) {
+        const R s = scale_of<R>(L);
+        Fx *= s;
+        Fy *= s;
+        Fz *= s;
+    }
+    collide<R, true, kS>(g, Fx, Fy, Fz, collide_const<R>(L), inv_scale_of<R>(L));
     // Rebuild the store addresses from here: an empty register barrier on the
     // cell index keeps the compiler from holding 19 precomputed 64-bit store
     // addresses live across the collision (38 VGPRs), so stores use the same
@@ -219,7 +235,7 @@ __device__ __forceinline__ void step_cell(const LatticeArgs& L, uint32_t cell) {
     uint32_t cs = cell;
     asm volatile("" : "+v"(cs));
     store_cell<Cd, PAT, (NT & 2) != 0>(PlaneTable{PAT == PAT_AB ? L.pb : L.pa}, cs, nb, g,
-                                       scale_of<R>(L));
+                                       kS ? R(1) : scale_of<R>(L));
 }
 
 }  // namespace lbm

@@ -51,6 +51,7 @@ hipError_t launch_tables(int precision, const LatticeArgs& L, const lbm_force_mo
 hipError_t launch_init(int precision, int pat, const LatticeArgs& L, int kind, double amp,
                        uint64_t seed, hipStream_t s);
 hipError_t launch_step(int precision, int pat, const LatticeArgs& L, hipStream_t s);
+hipError_t launch_stream(int precision, int pat, const LatticeArgs& L, hipStream_t s);
 hipError_t launch_diag(int precision, int pat, const LatticeArgs& L, double* partials,
                        int nblocks, double* result, hipStream_t s);
 hipError_t launch_moments(int precision, int pat, const LatticeArgs& L, double* rho, double* u,

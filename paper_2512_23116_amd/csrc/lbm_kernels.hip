@@ -26,6 +26,24 @@ __global__ __launch_bounds__(256) void k_step(LatticeArgs L) {
     step_cell<Cd, PAT, NT>(L, cell);
 }
 
+// Free streaming: the step's loads and stores with the identity for the
+// collision (no force, no arithmetic beyond the storage codec, exact for every
+// format).  Same block order, addressing and address barrier as k_step, so its
+// time is the ceiling of the step's access pattern.
+template <class Cd, int PAT>
+__global__ __launch_bounds__(256) void k_stream(LatticeArgs L) {
+    using R = typename Cd::R;
+    const uint32_t cell = block_id(L) * 256u + threadIdx.x;
+    if (cell >= L.ncell) return;
+    const CellPos p = decode(cell, L);
+    const Nbr nb = make_nbr(p, L);
+    R g[19];
+    load_cell<Cd, PAT>(PlaneTable{L.pa}, cell, nb, g, R(1));
+    uint32_t cs = cell;
+    asm volatile("" : "+v"(cs));
+    store_cell<Cd, PAT>(PlaneTable{PAT == PAT_AB ? L.pb : L.pa}, cs, nb, g, R(1));
+}
+
 // ----------------------------------------------------- diagnostics ---
 // Per-block FP64 partials: [0..3] sum of tau_t^p (p = 1..4, tau_t = tau_e - tau0),
 // [4] min tau_t, [5] max tau_t, [6] sum delta rho, [7..9] sum rho u,
@@ -416,6 +434,15 @@ hipError_t launch_step(int precision, int pat, const LatticeArgs& L, hipStream_t
             hipLaunchKernelGGL((k_step<Cd, P, 2>), grid_for(L.ncell), dim3(256), 0, s, L);
         else
             hipLaunchKernelGGL((k_step<Cd, P, 0>), grid_for(L.ncell), dim3(256), 0, s, L);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_stream(int precision, int pat, const LatticeArgs& L, hipStream_t s) {
+    return dispatch(precision, pat, [&](auto cd, auto pt) {
+        using Cd = decltype(cd);
+        constexpr int P = decltype(pt)::value;
+        hipLaunchKernelGGL((k_stream<Cd, P>), grid_for(L.ncell), dim3(256), 0, s, L);
         return hipGetLastError();
     });
 }

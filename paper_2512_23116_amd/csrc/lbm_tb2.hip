@@ -20,7 +20,7 @@
 // once per extended column (1024 / 868 of the interior, plus 2 planes per
 // chunk) and B is written once, instead of two full reads and writes.
 // Per cell the arithmetic is the single-step collision; for 16-bit storage
-// the LDS buffers hold values rounded through the storage codec, so the
+// the LDS buffers hold the intermediate level in the storage format, so the
 // result matches two single steps.
 #include "lbm_device.hpp"
 
@@ -40,13 +40,6 @@ struct TB2Args {
     uint32_t tiles_x, tiles_y, zchunk, nblocks;
 };
 
-template <class Cd>
-__device__ __forceinline__ typename Cd::R storage_round(typename Cd::R v, const LatticeArgs& L) {
-    using R = typename Cd::R;
-    if constexpr (std::is_same_v<typename Cd::T, R>) return v;
-    else return dec<Cd>(enc<Cd>(v, scale_of<R>(L)), inv_scale_of<R>(L));
-}
-
 __device__ __forceinline__ uint32_t wrap_add(uint32_t base, int d, uint32_t n) {
     // (base + d) mod n for base < n and -1 <= d <= 64 (n >= 1)
     int v = (int)base + d;
@@ -59,12 +52,21 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     constexpr int TB_TY = TB_EY - 2, TB_E = TB_EX * TB_EY;
     using T = typename Cd::T;
     using R = typename Cd::R;
-    static_assert(std::is_same_v<R, float>, "the LDS buffers hold FP32 values");
-    __shared__ R down[5][TB_E];      // c_z = -1 populations of plane z+1
-    __shared__ R mid[2][9][TB_E];    // c_z =  0 populations, planes z+1 and z
-    __shared__ R up[3][5][TB_E];     // c_z = +1 populations, planes z+1, z, z-1
-    __shared__ R rowbuf[2][TB_EY][16];  // force row coefficients of the phase-1 plane, per tile row
-    __shared__ R xbuf[TB_EX][4];        // x harmonics of the tile columns
+    static_assert(std::is_same_v<R, float>, "the collision runs in FP32");
+    // 16-bit storage: the intermediate level stays in LDS in the storage format
+    // (the values a single step would store), at 2 B per value.  That leaves room
+    // to rotate the buffers over more slots (down 2, mid 3, up 4: 57 values per
+    // column, 117 KB) so that phase 1 of the next plane may overwrite no slot
+    // phase 2 of this plane still reads: one barrier per plane.  FP32 storage
+    // keeps FP32 values in the minimal 38 slots (152 KB) and two barriers.
+    constexpr bool k16 = sizeof(T) == 2;
+    using LT = std::conditional_t<k16, T, R>;
+    constexpr int ND = k16 ? 2 : 1, NM = k16 ? 3 : 2, NU = k16 ? 4 : 3, NR = k16 ? 3 : 1;
+    __shared__ LT down[ND][5][TB_E];   // c_z = -1 populations of plane z+1
+    __shared__ LT mid[NM][9][TB_E];    // c_z =  0 populations, planes z+1, z (, z-1)
+    __shared__ LT up[NU][5][TB_E];     // c_z = +1 populations, planes z+1, z, z-1 (, z-2)
+    __shared__ R rowbuf[NR][TB_EY][16];  // force row coefficients of the phase-1 plane
+    __shared__ R xbuf[TB_EX][4];         // x harmonics of the tile columns
 
     const LatticeArgs& L = A.L;
     // one contiguous range of tiles per XCD whenever a block order is asked for
@@ -84,10 +86,29 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     const uint32_t x2 = X0 + (uint32_t)ex - 1u, y2 = Y0 + (uint32_t)ey - 1u;
     const bool inner = ex >= 1 && ex <= TB_TX && ey >= 1 && ey <= TB_TY && x2 < L.nx && y2 < L.ny;
 
+    // 16-bit storage: populations and force in units of 1/sigma (collide's
+    // kScaled), so that every pass through the storage format is a conversion
     const R inv_s = inv_scale_of<R>(L), s_st = scale_of<R>(L);
+    const R load_s = k16 ? R(1) : inv_s, store_s = k16 ? R(1) : s_st;
     const uint64_t pbytes = L.plane * (uint64_t)sizeof(T);
     const PlaneStride src{(char*)L.a, pbytes}, dst{(char*)L.b, pbytes};
     const CollideConst<R>& k = collide_const<R>(L);
+    // FP16: the array bases are made opaque inside the loop, so the compiler
+    // recomputes the 38 plane bases per use instead of keeping them live across
+    // it and spilling scalar registers to VGPR lanes (+1.4 % at 800^3; BF16 and
+    // FP32 measured 1 % / 0 % slower that way and keep the hoisted bases)
+    auto opaque_base = [&](char* p) -> char* {
+        if constexpr (std::is_same_v<Cd, CdF16>) asm volatile("" : "+s"(p));
+        return p;
+    };
+    auto to_lds = [&](R v) -> LT {
+        if constexpr (k16) return enc<Cd>(v, R(1));
+        else return v;
+    };
+    auto from_lds = [&](LT v) -> R {
+        if constexpr (k16) return dec<Cd>(v, R(1));
+        else return v;
+    };
 
     auto plane1 = [&](int j) {   // z of the phase-1 plane of iteration j: Z0 - 1 + j, wrapped
         int z = (int)Z0 - 1 + j;
@@ -102,50 +123,57 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
         p.z = plane1(j);
         p.row = y1 + L.ny * p.z;
         const Nbr nb = make_nbr(p, L);
-        load_cell<Cd, PAT_AB>(src, x1 + L.nx * p.row, nb, g, inv_s);
+        load_cell<Cd, PAT_AB>(PlaneStride{opaque_base(src.base), pbytes}, x1 + L.nx * p.row, nb,
+                              g, load_s);
     };
 
     // Force (eq. forcing_pattern via the row / x-harmonic tables).  With 16-bit
-    // storage the row coefficients of the next phase-1 plane are fetched one
-    // iteration ahead into LDS by the first 16 * TB_EY threads (one value each:
-    // tile row r, coefficient e) and the x harmonics of the 64 columns sit in LDS,
-    // so phase 1 waits on no table load (+9 % at 800^3).  With FP32 storage that
-    // costs more than it saves (-7 %): phase 1 reads the tables directly.
-    constexpr bool kLdsRows = sizeof(T) == 2;
+    // storage the row coefficients of a phase-1 plane are fetched two iterations
+    // ahead into LDS by the first 16 * TB_EY threads (one value each: tile row r,
+    // coefficient e) and the x harmonics of the 64 columns sit in LDS, so phase 1
+    // waits on no table load (+9 % at 800^3).  With FP32 storage that costs more
+    // than it saves (-7 %): phase 1 reads the tables directly.
     const bool forced = L.rowc != nullptr;
     const R* rowc = (const R*)L.rowc;
     const int rr = t >> 4, re = t & 15;           // for t < 16 * TB_EY
-    const bool row_loader = kLdsRows && forced && t < 16 * TB_EY;
+    const bool row_loader = k16 && forced && t < 16 * TB_EY;
     const uint32_t ry = wrap_add(Y0, rr - 1, L.ny);
     auto row_coeff = [&](int j) { return rowc[(uint64_t)(ry + L.ny * plane1(j)) * 16 + re]; };
-    if (kLdsRows) {
+    const int niter = nzc + 2;
+    if constexpr (k16) {
         if (forced && t < 4 * TB_EX)
             xbuf[t >> 2][t & 3] =
                 ((const R*)L.xtab)[(uint64_t)wrap_add(X0, (t >> 2) - 1, L.nx) * 4 + (t & 3)];
-        if (row_loader) rowbuf[0][rr][re] = row_coeff(0);
+        if (row_loader) {
+            rowbuf[0][rr][re] = row_coeff(0);
+            rowbuf[1][rr][re] = row_coeff(1);   // niter >= 3
+        }
         __syncthreads();
     }
 
     // One iteration j: phase 1 on the prefetched pulls P of plane Z0 - 1 + j,
     // then the pulls of plane j + 2 are issued into P (two planes of prefetch
     // in flight), then phase 2 on plane Z0 + j - 2.
-    const int niter = nzc + 2;
     // The phase-2 cell of iteration j is the phase-1 cell of iteration j - 1 (same
     // column, plane Z0 + j - 2): its force is carried over instead of recomputed.
     R Fpx = R(0), Fpy = R(0), Fpz = R(0);
     auto iteration = [&](int j, R (&P)[19]) {
+        const uint32_t uj = (uint32_t)j;
         R Fx = R(0), Fy = R(0), Fz = R(0);
         {   // phase 1: step t at plane Z0 - 1 + j for every extended column
             R g[19];
 #pragma unroll
             for (int i = 0; i < 19; ++i) g[i] = P[i];
-            if constexpr (kLdsRows) {
+            if constexpr (k16) {
                 if (forced) {
-                    const R* rc = rowbuf[j & 1][ey];
+                    const R* rc = rowbuf[uj % NR][ey];
                     const R s1 = xbuf[ex][0], c1 = xbuf[ex][1], s2 = xbuf[ex][2], c2 = xbuf[ex][3];
                     Fx = rc[0] + s1 * rc[3] + c1 * rc[6] + s2 * rc[9] + c2 * rc[12];
                     Fy = rc[1] + s1 * rc[4] + c1 * rc[7] + s2 * rc[10] + c2 * rc[13];
                     Fz = rc[2] + s1 * rc[5] + c1 * rc[8] + s2 * rc[11] + c2 * rc[14];
+                    Fx *= s_st;
+                    Fy *= s_st;
+                    Fz *= s_st;
                 }
             } else {
                 CellPos p;
@@ -155,47 +183,54 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
                 p.row = y1 + L.ny * p.z;
                 force_at<R>(L, p, Fx, Fy, Fz);
             }
-            collide<R, true>(g, Fx, Fy, Fz, k);
-            const int s2 = j & 1, s3 = j % 3;
+            collide<R, true, k16>(g, Fx, Fy, Fz, k, inv_s);
+            const uint32_t sd = uj % ND, sm = uj % NM, su = uj % NU;
             static_for<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int cz = cz_of(i), ii = zclass_index(i);
-                const R v = storage_round<Cd>(g[i], L);
-                if constexpr (cz < 0) down[ii][t] = v;
-                else if constexpr (cz == 0) mid[s2][ii][t] = v;
-                else up[s3][ii][t] = v;
+                const LT v = to_lds(g[i]);
+                if constexpr (cz < 0) down[sd][ii][t] = v;
+                else if constexpr (cz == 0) mid[sm][ii][t] = v;
+                else up[su][ii][t] = v;
             });
         }
         __syncthreads();
-        // (16-bit storage) the next plane's row coefficients, before the pulls
+        // (16-bit storage) the row coefficients of the phase-1 plane two iterations on
         R rnext = R(0);
-        const bool fetch = row_loader && j + 1 < niter;
-        if (fetch) rnext = row_coeff(j + 1);
+        const bool fetch = row_loader && j + 2 < niter;
+        if (fetch) rnext = row_coeff(j + 2);
         if (j + 2 < niter) pull(j + 2, P);
         if (j >= 2 && inner) {   // phase 2: step t+1 at plane Z0 + j - 2
             const uint32_t z2 = Z0 + (uint32_t)(j - 2);
             R g[19];
-            const int s2 = (j - 1) & 1, s3 = (j - 2) % 3;   // planes z2 and z2 - 1
+            // planes z2 + 1, z2 and z2 - 1: phase 1 of iterations j, j - 1, j - 2
+            const uint32_t sd = uj % ND, sm = (uj - 1) % NM, su = (uj - 2) % NU;
             static_for<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i), ii = zclass_index(i);
                 const int col = (ex - cx) + TB_EX * (ey - cy);
-                if constexpr (cz < 0) g[i] = down[ii][col];          // from plane z2 + 1
-                else if constexpr (cz == 0) g[i] = mid[s2][ii][col]; // from plane z2
-                else g[i] = up[s3][ii][col];                         // from plane z2 - 1
+                if constexpr (cz < 0) g[i] = from_lds(down[sd][ii][col]);
+                else if constexpr (cz == 0) g[i] = from_lds(mid[sm][ii][col]);
+                else g[i] = from_lds(up[su][ii][col]);
             });
-            collide<R, true>(g, Fpx, Fpy, Fpz, k);
+            collide<R, true, k16>(g, Fpx, Fpy, Fpz, k, inv_s);
             const uint32_t cell = x2 + L.nx * (y2 + L.ny * z2);
+            const PlaneStride out{opaque_base(dst.base), pbytes};
             static_for<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                *elem_ptr<T>(dst, i, cell) = enc<Cd>(g[i], s_st);
+                *elem_ptr<T>(out, i, cell) = enc<Cd>(g[i], store_s);
             });
         }
-        if (fetch) rowbuf[(j + 1) & 1][rr][re] = rnext;   // read after the next barrier
+        // read by phase 1 two iterations on, after the next barrier; the slot was
+        // last read by phase 1 of iteration j - 1, which every thread has passed
+        if (fetch) rowbuf[(uj + 2) % NR][rr][re] = rnext;
         Fpx = Fx;
         Fpy = Fy;
         Fpz = Fz;
-        __syncthreads();
+        // With the rotating 16-bit slots, phase 1 of iteration j + 1 writes no
+        // slot that phase 2 of iteration j reads, and phase 1 of j + 2 waits at
+        // the barrier of j + 1 for every phase 2 of j: no second barrier.
+        if constexpr (!k16) __syncthreads();
     };
 
     R pa[19], pb[19];

@@ -29,6 +29,7 @@ STREAMING = {"aa": LBM_STREAM_AA, "ab": LBM_STREAM_AB}
 # C-ABI entry points every build must export (checked by the CPU tests).
 EXPORTS = (
     "lbm_config_default", "lbm_required_bytes", "lbm_create", "lbm_init_seeded", "lbm_step",
+    "lbm_stream_only",
     "lbm_moments", "lbm_kt_stats", "lbm_kt_field", "lbm_kt_slice", "lbm_get_populations",
     "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_set_stream",
     "lbm_steps_done",
@@ -136,6 +137,7 @@ def lib():
         "lbm_create": (ctypes.c_int, [ctypes.POINTER(lbm_config), ctypes.POINTER(H)]),
         "lbm_init_seeded": (ctypes.c_int, [H, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64]),
         "lbm_step": (ctypes.c_int, [H, ctypes.c_int64]),
+        "lbm_stream_only": (ctypes.c_int, [H, ctypes.c_int64]),
         "lbm_moments": (ctypes.c_int, [H, dp, dp]),
         "lbm_kt_stats": (ctypes.c_int, [H, ctypes.POINTER(lbm_stats)]),
         "lbm_kt_field": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_float)]),
@@ -220,6 +222,10 @@ def lbm_init_seeded(h, kind, amplitude, seed):
 
 def lbm_step(h, n):
     _check(lib().lbm_step(h, n), h)
+
+
+def lbm_stream_only(h, n):
+    _check(lib().lbm_stream_only(h, n), h)
 
 
 def lbm_moments(h, ncell):
@@ -433,6 +439,12 @@ class Lattice:
     def step(self, n=1):
         """lbm_step: n time steps, asynchronous on the lattice's stream."""
         lbm_step(self.handle, n)
+        return self
+
+    def stream_only(self, n=1):
+        """lbm_stream_only: n steps of free streaming (the step's data movement,
+        no collision), asynchronous."""
+        lbm_stream_only(self.handle, n)
         return self
 
     def sync(self):
