@@ -1,5 +1,7 @@
 """Reduced-precision storage (FP16 / BF16 deviations, FP32 collision): error
 against the FP64 oracle is reported and bounded by the storage rounding."""
+import os
+
 import numpy as np
 import pytest
 
@@ -49,3 +51,76 @@ def test_fp16_scale_keeps_small_deviations(lbm):
     g = f - np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3]).reshape(19, 1, 1, 1)
     nz = np.abs(g[0]) > 0
     assert nz.sum() > 0.5 * g[0].size
+
+
+GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "precision256_oracle.json")
+
+# Bars after 1000 steps of the 256^3 workload (laminar spin-up from the noise start,
+# where perturbations do not grow), from the rounding each storage format adds per
+# step to every stored deviation, accumulated over n = 1000 steps:
+#   FP64  any evaluation order, ~1e-16 per step: 1e-10 (populations, velocity),
+#         1e-9 (spectrum, theta statistics);
+#   FP32  2^-24 relative per step, linear accumulation: n 2^-24 = 6e-5 (populations,
+#         velocity), twice that for the quadratic spectrum, 1e-3 for the theta
+#         statistics (differences of moments, as in the 10-step K_t parity);
+#   FP16  (sigma = 2^15) half an ulp of sigma g is at most 2^-12 of the value,
+#         about 4e-4 of the deviation scale per step; a random walk over n steps
+#         gives 1.2e-2: bar 3 x that, twice for the spectrum and theta statistics;
+#   BF16  half an ulp is 2^-9 of the value, 2e-3 per step, 6e-2 over n steps as a
+#         random walk: bar 3 x that.
+PRECISION_256_BARS = {
+    "fp64": dict(f=1e-10, u=1e-10, spec=1e-9, theta=1e-9),
+    "fp32": dict(f=6e-5, u=6e-5, spec=1.2e-4, theta=1e-3),
+    "fp16": dict(f=4e-2, u=4e-2, spec=8e-2, theta=8e-2),
+    "bf16": dict(f=0.2, u=0.2, spec=0.4, theta=0.4),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
+def test_precision_256_against_the_oracle(lbm, precision):
+    """The precision-study workload (forced-HIT LES 256^3, 16-mode forcing, 1e-3 noise
+    start, C_s = 0.1) in each storage format, 1000 steps, against the FP64 C
+    oracle's record of the same run (tests/golden/precision256_oracle.json, written
+    by tests/golden/make_precision256_reference.py from oracle/ alone): sampled
+    populations and velocities, the spectrum E(k) for k <= 64 and the theta
+    statistics at steps 500 and 1000."""
+    import json
+    from paper_2512_23116_amd.inputs import random_solenoidal_modes
+    g = json.load(open(GOLDEN_256))
+    if len(g["snapshots"]) < 3:
+        pytest.skip("the oracle reference is incomplete")
+    N = g["N"]
+    modes = random_solenoidal_modes(g["F0"], g["force_seed"])
+    lat = lbm.Lattice((N, N, N), g["tau0"], g["C"], modes, precision=precision,
+                      streaming="aa", smag_form=g["smag_form"])
+    lat.init(lbm.LBM_INIT_NOISE, g["noise"], g["init_seed"])
+    zyx = g["sample_cells_zyx"]
+    cells = np.array([x + N * (y + N * z) for z, y, x in zyx])
+    nf = g["n_f_sample"]
+    bars = PRECISION_256_BARS[precision]
+    for snap in g["snapshots"][1:]:
+        lat.step(snap["step"] - lat.steps)
+        st = lat.stats()
+        E = lat.spectrum(64)
+        f = lat.sample(cells[:nf])
+        _, u = lat.moments()
+        u_s = np.array([u[:, z, y, x] for z, y, x in zyx])
+        f_o = np.array(snap["f_sample"])
+        u_o = np.array(snap["u_sample"])
+        W = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3])
+        e_f = float(np.abs(f - f_o).max() / np.abs(f_o - W).max())
+        e_u = float(np.sqrt(((u_s - u_o) ** 2).sum() / (u_o ** 2).sum()))
+        E_o = np.array(snap["spectrum"])
+        e_spec = {K: float(np.max(np.abs(E[1:K + 1] / E_o[1:K + 1] - 1))) for K in (8, 32, 64)}
+        th = snap["theta"]
+        e_th = {k: abs(st["theta_" + k] - th[k]) / abs(th[k]) for k in ("mean", "var", "flat")}
+        e_E = abs(st["energy"] - snap["energy"]) / snap["energy"]
+        print(f"256^3 {precision} step {snap['step']} vs oracle: populations {e_f:.2e}, "
+              f"u {e_u:.2e}, spectrum k<=8/32/64 {e_spec[8]:.2e}/{e_spec[32]:.2e}/"
+              f"{e_spec[64]:.2e}, theta mean/var/flat {e_th['mean']:.2e}/{e_th['var']:.2e}/"
+              f"{e_th['flat']:.2e}, energy {e_E:.2e}", flush=True)
+        assert e_f <= bars["f"] and e_u <= bars["u"]
+        assert e_spec[64] <= bars["spec"] and e_E <= bars["spec"]
+        assert max(e_th.values()) <= bars["theta"]
+    lat.close()
