@@ -369,9 +369,11 @@ def profile_run(lbm, params, args):
                  (args.large_N, p, "ab", 2, 8)]
         if not args.no_precision:
             runs += [(args.large_N, "fp16", "aa", 0, 4), (args.large_N, "bf16", "aa", 0, 4),
-                     (args.large_N, "fp16", "ab", 2, 8)]
+                     (args.large_N, "fp16", "ab", 2, 8), (args.large_N, "bf16", "ab", 2, 8)]
     for N, prec, streaming, tb, steps in runs:
-        run_lattice(lbm, params, N, prec, streaming, steps, 2, 0, spg=0, tb=tb)
+        # (AA and A/B one-step runs also time 4 launches of free streaming and 4 steps)
+        run_lattice(lbm, params, N, prec, streaming, steps, 2, 0, spg=0, tb=tb,
+                    ceiling=4 if tb == 0 and N == args.large_N else 0)
         log(f"profile: {N}^3 {prec} {streaming}{' two-step' if tb else ''}, "
             f"{steps} steps of plain launches done")
 

@@ -81,7 +81,7 @@ def lattice_key(kernel, grid, precision, tb2_n):
 
 
 def _csv(d, suffix):
-    files = glob.glob(os.path.join(d, f"*{suffix}"))
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
     if not files:
         raise FileNotFoundError(f"no *{suffix} under {d}")
     return list(csv.DictReader(open(files[0])))
@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--cmd", default="")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--streaming", default="aa")
+    ap.add_argument("--sq", help="rocprofv3 --pmc run of SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+                                  "SQ_INSTS_VALU SQ_WAIT_ANY SQ_INSTS_LDS GRBM_GUI_ACTIVE")
     ap.add_argument("--traffic-out")
     ap.add_argument("--durations-out")
     ap.add_argument("--tb2-n", type=int, default=800,
@@ -192,6 +194,50 @@ def main():
             acc[3] = fam
         if a.traffic_out:
             write_traffic(a.traffic_out, per_key)
+    if a.sq:
+        sq_table(a.sq, a.precision, a.tb2_n)
+
+
+def sq_table(d, precision, tb2_n, simds=1024, clock_ghz=2.4):
+    """Per step kernel and lattice: VALU instructions per cell update, an estimate
+    of how busy the SIMDs' VALUs were, the share of wave time spent waiting, and
+    the launch duration from the busy cycles.
+
+    VALU per cell update = SQ_INSTS_VALU (wave instructions) x 64 lanes / cell
+    updates of the launch (N^3, or 2 N^3 for the two-step kernel).  GRBM_GUI_ACTIVE
+    sums the busy cycles of the 8 XCDs, so /8 is one XCD's.  VALU busy (estimate) =
+    4 cycles x SQ_INSTS_VALU / (SIMDs x one XCD's busy cycles), a lower bound where
+    instructions take more than 4 cycles."""
+    rows = _csv(d, "_counter_collection.csv")
+    by = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        k = r["Kernel_Name"]
+        g = int(r["Grid_Size"])
+        by[(k, g)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    print("\nSQ counters (means over the launches of each kernel and lattice)")
+    print(f"{'kernel':40s} {'lattice':>16s} {'launches':>8s} {'VALU/update':>11s} "
+          f"{'VALU busy':>9s} {'wait/wave':>9s} {'LDS/update':>10s} {'us':>9s}")
+    for (k, g), c in sorted(by.items()):
+        lk = lattice_key(k, g, precision, tb2_n)
+        if lk is None and not short(k).startswith("k_stream<"):
+            continue
+        if lk is None:
+            N = round(g ** (1 / 3))
+            key, updates = f"{N}_stream", N ** 3
+        else:
+            fam, key = lk
+            N = int(key.split("_")[0])
+            updates = N ** 3 * (2 if fam == "k_step_tb2" else 1)
+        need = ("SQ_INSTS_VALU", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "GRBM_GUI_ACTIVE")
+        if not all(n in c for n in need):
+            continue
+        valu = statistics.mean(c["SQ_INSTS_VALU"])
+        gui = statistics.mean(c["GRBM_GUI_ACTIVE"]) / 8
+        wait = statistics.mean(c["SQ_WAIT_ANY"]) / statistics.mean(c["SQ_WAVE_CYCLES"])
+        lds = statistics.mean(c["SQ_INSTS_LDS"]) * 64 / updates if "SQ_INSTS_LDS" in c else float("nan")
+        print(f"{short(k)[:40]:40s} {key:>16s} {len(c['SQ_INSTS_VALU']):8d} "
+              f"{valu * 64 / updates:11.1f} {4 * valu / (simds * gui):9.2f} {wait:9.2f} "
+              f"{lds:10.1f} {gui / (clock_ghz * 1e3):9.1f}")
 
 
 def write_table(path, per_key, fmt, fam_col):
