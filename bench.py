@@ -121,8 +121,9 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
     """The headline workload: `repeats` timed runs of `intervals` snapshot
     intervals each.  One interval = `interval` lattice steps (one graph replay)
     and then the K_t statistics, the K_t map of the mid-z plane and the spectrum
-    E(k <= N/2) of the state reached.  The `warmup` intervals before the first
-    repeat capture the graph and create the FFT plan and the analysis buffers."""
+    E(k <= N/2) of the state reached, all collected before the repeat's clock
+    stops.  The `warmup` intervals before the first repeat capture the graph and
+    create the FFT plan and the analysis buffers."""
     import torch
     stream = torch.cuda.Stream()
     cfg = params.forced_hit(N)
@@ -133,12 +134,14 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
     lat.init(lbm.LBM_INIT_NOISE, cfg["noise"], cfg["init_seed"])
     kmax, zmid = N // 2, N // 2
 
-    def snapshot():
-        return lat.stats(), lat.kt_slice(zmid), lat.spectrum(kmax)
-
+    # Each interval's snapshot (statistics, K_t map of the mid plane, spectrum) is
+    # enqueued right after its steps and collected once the next interval's steps
+    # are enqueued too (lbm_snapshot_begin / _end): the device never waits for the
+    # host between intervals.
     for _ in range(warmup):
         lat.step(interval)
-        snapshot()
+        lat.snapshot_begin(kmax, zmid)
+        lat.snapshot_end()
     lat.sync()
     torch.cuda.synchronize()
     reps, last = [], None
@@ -146,14 +149,17 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
         events = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(intervals):
+        for i in range(intervals):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             lat.step(interval)
             e1.record(stream)
             events.append((e0, e1))
-            last = snapshot()
+            if i > 0:
+                last = lat.snapshot_end()
+            lat.snapshot_begin(kmax, zmid)
+        last = lat.snapshot_end()
         lat.sync()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -162,7 +168,7 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
         reps.append(dict(wall_s=wall, mlups=cells / wall / 1e6,
                          ms_per_step=wall / intervals * 1e3,
                          avg_launch_us=kern_s / (intervals * interval) * 1e6))
-    st, sl, E = last
+    st, E, sl = last
     steps_done = lat.steps
     ceil = pattern_ceiling(lat, stream, 200)
     lat.close()
@@ -553,7 +559,9 @@ def main():
                          f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
                          f"forcing, 1e-3 noise start; one step = {args.diag_every} lattice "
                          f"steps (one graph replay) + K_t/theta statistics + K_t map of the "
-                         f"mid-z plane to host + energy spectrum E(k<={args.N // 2}); "
+                         f"mid-z plane to host + energy spectrum E(k<={args.N // 2}) "
+                         f"(lbm_snapshot_begin/_end: the next interval is enqueued before "
+                         f"the host waits; every snapshot is collected inside the timed region); "
                          f"{args.steps} steps ({args.steps * args.diag_every} lattice steps, "
                          f"{args.steps} snapshots of each diagnostic) timed per repeat, "
                          f"median of {args.repeats} repeats after {args.warmup} warm-up steps"),

@@ -253,6 +253,25 @@ lbm_status lbm_theta_histogram(lbm_handle* h, double lo, double hi, int32_t nbin
 lbm_status lbm_theta_histogram_noalloc(lbm_handle* h, double lo, double hi, int32_t nbins,
                                        int64_t* counts);
 
+/* Snapshot of the current state for a run that keeps stepping: its statistics
+ * (as lbm_kt_stats), the K_t map of plane z (as lbm_kt_slice) and its spectrum
+ * E[0..kmax] (as lbm_spectrum), without waiting for them.
+ * lbm_snapshot_begin enqueues on the handle's stream, in order with the steps,
+ * the kernels that read the state (reductions, K_t plane, velocity), the FFTs
+ * and shell sums of the velocity, and the copies of the results to page-locked
+ * host memory, and returns at once: the caller can enqueue the next lbm_step
+ * before it waits, so the device never idles on the host.
+ * lbm_snapshot_end waits for the snapshot and writes its results: stats (as
+ * lbm_kt_stats, steps = the step count at lbm_snapshot_begin), E (host
+ * double[kmax+1]) and kt_plane (host float[nx*ny]); any may be NULL.
+ * 0 <= kmax <= 4096, 0 <= z < nz, else INVALID_ARG.  One snapshot per handle
+ * at a time: begin while one is pending, or end with none pending, is
+ * LBM_ERR_STATE, and so are the other analysis calls (spectra, structure
+ * functions, turbulence scales) until lbm_snapshot_end.  UNSTABLE as in
+ * lbm_kt_stats.  Buffers are kept until lbm_destroy. */
+lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z);
+lbm_status lbm_snapshot_end(lbm_handle* h, lbm_stats* stats, double* E, float* kt_plane);
+
 /* Shell-binned kinetic-energy spectrum of the current state (Sec. 2.2,
  * eq. integral_length_scale with the squared modulus):
  *   E[k] = 1/2 sum_{k - 1/2 <= |q| < k + 1/2} |u_hat(q)|^2,  u_hat = FFT(u) / ncells,

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "lbm_device.hpp"
+#include "lbm_observe.hpp"
 
 namespace lbm {
 
@@ -200,10 +201,29 @@ struct AnalysisCache {
     size_t out_elems = 0;
     hipfftHandle plan = nullptr;
     bool has_plan = false;
+    // snapshot (lbm_snapshot_begin / _end): completion event, the device K_t
+    // plane and the page-locked results
+    hipEvent_t ev_snap = nullptr;
+    float* d_plane = nullptr;
+    double* h_sums = nullptr;        // kStatSums reduced sums
+    double* h_E = nullptr;           // spectrum, h_E_elems
+    size_t h_E_elems = 0;
+    float* h_plane = nullptr;        // nx * ny
+    bool snap_pending = false;
+    int snap_kmax = 0;
+    int64_t snap_steps = 0;
 };
 
 void release_analysis(AnalysisCache* a) {
     if (!a) return;
+    if (a->ev_snap) {
+        (void)hipEventSynchronize(a->ev_snap);
+        (void)hipEventDestroy(a->ev_snap);
+    }
+    if (a->d_plane) (void)hipFree(a->d_plane);
+    if (a->h_sums) (void)hipHostFree(a->h_sums);
+    if (a->h_E) (void)hipHostFree(a->h_E);
+    if (a->h_plane) (void)hipHostFree(a->h_plane);
     if (a->has_plan) (void)hipfftDestroy(a->plan);
     if (a->hist) (void)hipFree(a->hist);
     if (a->u) (void)hipFree(a->u);
@@ -237,6 +257,8 @@ hipError_t ensure(T*& p, size_t& have, size_t n) {
 // Velocity (FP64, [3][ncell]) of the current state into the cached buffer.
 lbm_status velocity(lbm_handle* h, const double** u) {
     AnalysisCache& a = cache(h);
+    if (a.snap_pending)
+        return set_err(h, LBM_ERR_STATE, "a snapshot is pending (lbm_snapshot_end first)");
     const size_t nc = h->args.ncell;
     if (!a.u) {
         hipError_t e = hipMalloc((void**)&a.u, 3 * nc * sizeof(double));
@@ -252,8 +274,9 @@ lbm_status velocity(lbm_handle* h, const double** u) {
     return LBM_OK;
 }
 
-// The handle's D2Z plan of its lattice (created on first use), bound to its stream.
-lbm_status fft_plan(lbm_handle* h, AnalysisCache& a) {
+// The handle's D2Z plan of its lattice (created on first use), bound to `stream`
+// (the handle's stream by default).
+lbm_status fft_plan(lbm_handle* h, AnalysisCache& a, hipStream_t stream) {
     if (!a.has_plan) {
         hipfftResult fr = hipfftPlan3d(&a.plan, (int)h->args.nz, (int)h->args.ny,
                                        (int)h->args.nx, HIPFFT_D2Z);
@@ -261,7 +284,7 @@ lbm_status fft_plan(lbm_handle* h, AnalysisCache& a) {
             return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlan3d: ") + fft_error(fr));
         a.has_plan = true;
     }
-    hipfftResult fr = hipfftSetStream(a.plan, h->stream);
+    hipfftResult fr = hipfftSetStream(a.plan, stream);
     if (fr != HIPFFT_SUCCESS)
         return set_err(h, LBM_ERR_DEVICE, std::string("hipfftSetStream: ") + fft_error(fr));
     return LBM_OK;
@@ -285,7 +308,7 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
     if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(spectrum)");
-    st = fft_plan(h, a);
+    st = fft_plan(h, a, h->stream);
     if (st != LBM_OK) return st;
     hipfftResult fr = HIPFFT_SUCCESS;
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
@@ -303,6 +326,87 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (e == hipSuccess) e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "spectrum");
+    return LBM_OK;
+}
+
+lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    if (kmax < 0 || kmax > 4096) return set_err(h, LBM_ERR_INVALID_ARG, "kmax must be 0..4096");
+    if (z < 0 || (uint32_t)z >= h->args.nz) return set_err(h, LBM_ERR_INVALID_ARG, "z outside 0..nz-1");
+    if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
+    AnalysisCache& a = cache(h);
+    if (a.snap_pending) return set_err(h, LBM_ERR_STATE, "a snapshot is already pending");
+    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
+    const size_t nc = h->args.ncell, nxy = h->args.nxy, nmodes = (nx / 2 + 1) * (size_t)ny * nz;
+    // buffers, created on first use and kept until lbm_destroy
+    hipError_t e = hipSuccess;
+    if (!a.u) e = hipMalloc((void**)&a.u, 3 * nc * sizeof(double));
+    if (e == hipSuccess) e = ensure(a.c, a.c_elems, nmodes);
+    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
+    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
+    if (e == hipSuccess && !a.d_plane) e = hipMalloc((void**)&a.d_plane, nxy * sizeof(float));
+    if (e == hipSuccess && !a.h_sums) e = hipHostMalloc((void**)&a.h_sums, kDiagSlots * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess && !a.h_plane) e = hipHostMalloc((void**)&a.h_plane, nxy * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess && a.h_E_elems < (size_t)kmax + 1) {
+        if (a.h_E) (void)hipHostFree(a.h_E);
+        a.h_E = nullptr;
+        a.h_E_elems = 0;
+        e = hipHostMalloc((void**)&a.h_E, ((size_t)kmax + 1) * sizeof(double), hipHostMallocDefault);
+        if (e == hipSuccess) a.h_E_elems = (size_t)kmax + 1;
+    }
+    if (e == hipSuccess && !a.ev_snap) e = hipEventCreateWithFlags(&a.ev_snap, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_err(h, e, "snapshot buffers");
+    lbm_status st = fft_plan(h, a, h->stream);
+    if (st != LBM_OK) return st;
+    // everything on the handle's stream, in order with the steps: the state reads,
+    // the transforms of the velocity and the copies to page-locked memory
+    double* sums = nullptr;
+    e = launch_stats(h, &sums);
+    const int pat = current_pattern(h);
+    const LatticeArgs args = current_args(h);
+    if (e == hipSuccess) e = launch_ktslice(h->cfg.precision, pat, args, (uint32_t)z, a.d_plane, h->stream);
+    if (e == hipSuccess) e = launch_moments(h->cfg.precision, pat, args, nullptr, a.u, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a.h_sums, sums, kStatSums * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a.h_plane, a.d_plane, nxy * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "snapshot (state reads)");
+    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
+    const size_t shm = (size_t)(kmax + 1) * sizeof(double);
+    hipfftResult fr = HIPFFT_SUCCESS;
+    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
+        fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(a.u + (size_t)c * nc), a.c);
+        if (fr != HIPFFT_SUCCESS) break;
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
+                           (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
+                           (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
+    }
+    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(a.h_E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(a.ev_snap, h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "snapshot (spectrum)");
+    a.snap_pending = true;
+    a.snap_kmax = kmax;
+    a.snap_steps = h->steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_snapshot_end(lbm_handle* h, lbm_stats* stats, double* E, float* kt_plane) {
+    if (!h) return LBM_ERR_INVALID_ARG;
+    AnalysisCache* a = h->ana;
+    if (!a || !a->snap_pending) return set_err(h, LBM_ERR_STATE, "no snapshot is pending");
+    a->snap_pending = false;
+    const hipError_t e = hipEventSynchronize(a->ev_snap);
+    if (e != hipSuccess) return hip_err(h, e, "snapshot");
+    if (E) memcpy(E, a->h_E, ((size_t)a->snap_kmax + 1) * sizeof(double));
+    if (kt_plane) memcpy(kt_plane, a->h_plane, h->args.nxy * sizeof(float));
+    if (stats) {
+        fill_stats(h, a->h_sums, a->snap_steps, stats);
+        if (stats->n_nonfinite > 0)
+            return set_err(h, LBM_ERR_UNSTABLE, std::to_string(stats->n_nonfinite) + " non-finite cells");
+    }
     return LBM_OK;
 }
 
@@ -345,7 +449,7 @@ lbm_status lbm_spectra_1d(lbm_handle* h, int32_t kmax, double* E, double* ic) {
     if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * cols);
     if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)3 * cols);
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(one-dimensional spectra)");
-    st = fft_plan(h, a);
+    st = fft_plan(h, a, h->stream);
     if (st != LBM_OK) return st;
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     hipfftResult fr = HIPFFT_SUCCESS;

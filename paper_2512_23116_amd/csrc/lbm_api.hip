@@ -11,6 +11,7 @@
 
 #include "d3q19_mrt.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_observe.hpp"
 
 using namespace lbm;
 
@@ -209,6 +210,56 @@ LatticeArgs current_args(const lbm_handle* h) {
 void advance(lbm_handle* h) {
     h->steps += 1;
     if (h->cfg.streaming == LBM_STREAM_AB) h->cur ^= 1;
+}
+
+hipError_t launch_stats(lbm_handle* h, double** result) {
+    const uint64_t nc = h->args.ncell;
+    const int nb = (int)std::min<uint64_t>(kDiagBlocks, (nc + 255) / 256);
+    *result = h->partials + (size_t)kDiagBlocks * kDiagSlots;
+    return launch_diag(h->cfg.precision, current_pattern(h), current_args(h), h->partials, nb,
+                       *result, h->stream);
+}
+
+void fill_stats(const lbm_handle* h, const double* r, int64_t steps, lbm_stats* out) {
+    const uint64_t nc = h->args.ncell;
+    memset(out, 0, sizeof *out);
+    out->n_cells = (int64_t)nc;
+    out->steps = steps;
+    out->n_nonfinite = (int64_t)r[12];
+    const double n = (double)nc - r[12];
+    const double th0 = h->cfg.tau0 - 0.5;
+    // central moments of tau_t = theta - theta0 from its raw power sums
+    const double m1 = r[0] / n, e2 = r[1] / n, e3 = r[2] / n, e4 = r[3] / n;
+    double var = e2 - m1 * m1;
+    if (var < 0.0) var = 0.0;
+    const double mu3 = e3 - 3.0 * m1 * e2 + 2.0 * m1 * m1 * m1;
+    const double mu4 = e4 - 4.0 * m1 * e3 + 6.0 * m1 * m1 * e2 - 3.0 * m1 * m1 * m1 * m1;
+    const double skew = var > 0.0 ? mu3 / (var * sqrt(var)) : NAN;
+    const double flat = var > 0.0 ? mu4 / (var * var) : NAN;
+    out->theta_mean = th0 + m1;
+    out->theta_var = var;
+    out->theta_skew = skew;
+    out->theta_flat = flat;
+    out->theta_min = th0 + r[4];
+    out->theta_max = th0 + r[5];
+    const double s3 = 1.7320508075688772;   // K_t = sqrt(3) theta (ell = delta_x)
+    out->kt_mean = s3 * out->theta_mean;
+    out->kt_var = 3.0 * var;
+    out->kt_skew = skew;
+    out->kt_flat = flat;
+    out->kt_min = s3 * out->theta_min;
+    out->kt_max = s3 * out->theta_max;
+    out->mass = (double)nc * h->cfg.rho0 + r[6];
+    out->momentum[0] = r[7];
+    out->momentum[1] = r[8];
+    out->momentum[2] = r[9];
+    out->energy = r[10] / n;
+    out->energy_rho = r[11] / n;
+    out->strain2 = r[13] / n;
+    out->nut_strain2 = r[14] / (3.0 * n);   // nu_t = tau_t / 3
+    out->injection = r[15] / n;
+    for (int a = 0; a < 3; ++a) out->u_mean[a] = r[16 + a] / n;
+    for (int a = 0; a < 6; ++a) out->uu[a] = r[19 + a] / n;
 }
 
 }  // namespace lbm
@@ -435,55 +486,14 @@ lbm_status lbm_moments(lbm_handle* h, double* rho, double* u) {
 lbm_status lbm_kt_stats(lbm_handle* h, lbm_stats* out) {
     if (!h || !out) return h ? fail(h, LBM_ERR_INVALID_ARG, "out is NULL") : LBM_ERR_INVALID_ARG;
     if (!h->initialized) return fail(h, LBM_ERR_STATE, "state not initialised");
-    const uint64_t nc = h->args.ncell;
-    const int nb = (int)std::min<uint64_t>(kDiagBlocks, (nc + 255) / 256);
-    double* result = h->partials + (size_t)kDiagBlocks * kDiagSlots;
-    hipError_t e = launch_diag(h->cfg.precision, current_pattern(h), current_args(h), h->partials, nb,
-                               result, h->stream);
+    double* result = nullptr;
+    hipError_t e = launch_stats(h, &result);
     if (e != hipSuccess) return hip_fail(h, e, "diagnostic kernel");
     double r[kDiagSlots];
-    HIPCHK(h, hipMemcpyAsync(r, result, 25 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(r, result, kStatSums * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     lbm_status st = sync(h);
     if (st != LBM_OK) return st;
-
-    memset(out, 0, sizeof *out);
-    out->n_cells = (int64_t)nc;
-    out->steps = h->steps;
-    out->n_nonfinite = (int64_t)r[12];
-    const double n = (double)nc - r[12];
-    const double th0 = h->cfg.tau0 - 0.5;
-    // central moments of tau_t = theta - theta0 from its raw power sums
-    const double m1 = r[0] / n, e2 = r[1] / n, e3 = r[2] / n, e4 = r[3] / n;
-    double var = e2 - m1 * m1;
-    if (var < 0.0) var = 0.0;
-    const double mu3 = e3 - 3.0 * m1 * e2 + 2.0 * m1 * m1 * m1;
-    const double mu4 = e4 - 4.0 * m1 * e3 + 6.0 * m1 * m1 * e2 - 3.0 * m1 * m1 * m1 * m1;
-    const double skew = var > 0.0 ? mu3 / (var * sqrt(var)) : NAN;
-    const double flat = var > 0.0 ? mu4 / (var * var) : NAN;
-    out->theta_mean = th0 + m1;
-    out->theta_var = var;
-    out->theta_skew = skew;
-    out->theta_flat = flat;
-    out->theta_min = th0 + r[4];
-    out->theta_max = th0 + r[5];
-    const double s3 = 1.7320508075688772;   // K_t = sqrt(3) theta (ell = delta_x)
-    out->kt_mean = s3 * out->theta_mean;
-    out->kt_var = 3.0 * var;
-    out->kt_skew = skew;
-    out->kt_flat = flat;
-    out->kt_min = s3 * out->theta_min;
-    out->kt_max = s3 * out->theta_max;
-    out->mass = (double)nc * h->cfg.rho0 + r[6];
-    out->momentum[0] = r[7];
-    out->momentum[1] = r[8];
-    out->momentum[2] = r[9];
-    out->energy = r[10] / n;
-    out->energy_rho = r[11] / n;
-    out->strain2 = r[13] / n;
-    out->nut_strain2 = r[14] / (3.0 * n);   // nu_t = tau_t / 3
-    out->injection = r[15] / n;
-    for (int a = 0; a < 3; ++a) out->u_mean[a] = r[16 + a] / n;
-    for (int a = 0; a < 6; ++a) out->uu[a] = r[19 + a] / n;
+    fill_stats(h, r, h->steps, out);
     if (out->n_nonfinite > 0)
         return fail(h, LBM_ERR_UNSTABLE, "%lld non-finite cells", (long long)out->n_nonfinite);
     return LBM_OK;

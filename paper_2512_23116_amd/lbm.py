@@ -38,6 +38,7 @@ EXPORTS = (
     "lbm_theta_histogram_noalloc",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_theta_histogram", "lbm_spectrum", "lbm_spectra_1d", "lbm_structure_functions",
+    "lbm_snapshot_begin", "lbm_snapshot_end",
     "lbm_turbulence",
 )
 
@@ -154,6 +155,9 @@ def lib():
                                                        ctypes.c_int32,
                                                        ctypes.POINTER(ctypes.c_int64)]),
         "lbm_spectrum": (ctypes.c_int, [H, ctypes.c_int32, dp]),
+        "lbm_snapshot_begin": (ctypes.c_int, [H, ctypes.c_int32, ctypes.c_int32]),
+        "lbm_snapshot_end": (ctypes.c_int, [H, ctypes.POINTER(lbm_stats), dp,
+                                            ctypes.POINTER(ctypes.c_float)]),
         "lbm_spectra_1d": (ctypes.c_int, [H, ctypes.c_int32, dp, dp]),
         "lbm_structure_functions": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int32),
                                                    ctypes.c_int32, dp]),
@@ -313,6 +317,21 @@ def lbm_spectrum(h, kmax):
     E = np.empty(kmax + 1)
     _check(lib().lbm_spectrum(h, kmax, _dp(E)), h)
     return E
+
+
+def lbm_snapshot_begin(h, kmax, z):
+    _check(lib().lbm_snapshot_begin(h, kmax, z), h)
+
+
+def lbm_snapshot_end(h, kmax, nxy, allow_unstable=False):
+    st = lbm_stats()
+    E = np.empty(kmax + 1)
+    plane = np.empty(nxy, dtype=np.float32)
+    status = lib().lbm_snapshot_end(h, ctypes.byref(st), _dp(E),
+                                    plane.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    if not (allow_unstable and status == LBM_ERR_UNSTABLE):
+        _check(status, h)
+    return st.as_dict(), E, plane
 
 
 def lbm_spectra_1d(h, kmax, with_ic=True):
@@ -502,6 +521,19 @@ class Lattice:
     def spectrum(self, kmax):
         """lbm_spectrum: shell spectrum E(0..kmax)."""
         return lbm_spectrum(self.handle, kmax)
+
+    def snapshot_begin(self, kmax, z):
+        """lbm_snapshot_begin: enqueue the statistics, the K_t map of plane z and the
+        spectrum E(0..kmax) of the current state; returns at once."""
+        lbm_snapshot_begin(self.handle, kmax, z)
+        self._snap_kmax = kmax
+
+    def snapshot_end(self, allow_unstable=False):
+        """lbm_snapshot_end: (stats dict, E[0..kmax], K_t plane (ny, nx)) of the
+        snapshot begun last."""
+        st, E, plane = lbm_snapshot_end(self.handle, self._snap_kmax,
+                                        self.shape[1] * self.shape[2], allow_unstable)
+        return st, E, plane.reshape(self.shape[1:])
 
     def spectra_1d(self, kmax, with_ic=True):
         """lbm_spectra_1d: (E[c, a, k] of shape (3, 3, kmax+1), IC(k) or None)."""
