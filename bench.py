@@ -52,12 +52,12 @@ DURATION_TABLE = "durations_step_kernels_forced_hit_100_800.txt"
 
 def _profile_row(table, workload_key, family):
     """The row of a committed per-lattice profile table for this lattice, if it was
-    taken on the current sources of that kernel (else None)."""
-    from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
+    taken on the machine code of that kernel in the built library (else None)."""
+    from paper_2512_23116_amd.rocprof_summary import kernel_code_sha
     path = os.path.join(ROOT, "profiles", table)
     if not os.path.exists(path):
         return None
-    sha = kernel_source_sha(family)
+    sha = kernel_code_sha(family)
     for line in open(path):
         parts = line.split()
         if len(parts) >= 5 and not line.startswith("#") and parts[0] == workload_key \
@@ -68,14 +68,14 @@ def _profile_row(table, workload_key, family):
 
 def counter_traffic(workload_key, family="k_step"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current sources of that kernel (else None)."""
+    taken on the machine code of that kernel in the built library (else None)."""
     parts = _profile_row(TRAFFIC_TABLE, workload_key, family)
     return None if parts is None else float(parts[2]) + float(parts[3])
 
 
 def profile_launch_us(workload_key, family="k_step"):
     """Mean duration of one step launch in the committed rocprofv3 kernel trace of
-    this command, if it was taken on the current kernel sources (else None)."""
+    this command, if it was taken on the machine code in the built library (else None)."""
     parts = _profile_row(DURATION_TABLE, workload_key, family)
     return None if parts is None else float(parts[2])
 

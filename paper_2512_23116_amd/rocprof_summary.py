@@ -14,7 +14,8 @@ counters to bytes (FETCH_SIZE reads half of the true bytes on MI355X), and the
 calibrated bytes per step launch are compared with the algorithmic 2*19*b*N^3.
 With ``--traffic-out`` one line per lattice is appended for bench.py:
 ``<N>_<precision>_<streaming>[_tb2] <kernel-source sha> <fetch bytes> <write bytes>``,
-the sha taken over the sources that kernel is compiled from (KERNEL_SOURCES).
+the sha taken over that kernel family's gfx950 machine code in the built library
+(kernel_code_sha).
 With ``--durations-out`` the trace's mean duration per step launch is written
 the same way (``<key> <sha> <mean us> <launches> <family>``), so that bench.py can
 print the profile's figure beside its own live HIP-event mean.
@@ -26,27 +27,93 @@ import glob
 import hashlib
 import os
 import statistics
+import struct
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
-# Sources each step kernel is compiled from: its counters stay valid while these
-# files are unchanged.
-_COMMON = ("d3q19_mrt.hpp", "lbm_device.hpp", "lbm_internal.hpp", "lbm_index.hpp")
-KERNEL_SOURCES = {
-    "k_step": ("lbm_kernels.hip",) + _COMMON,
-    "k_step_tb2": ("lbm_tb2.hip",) + _COMMON,
-}
+# Mangled-name marker of each step-kernel family in the gfx950 code objects.
+KERNEL_FAMILIES = {"k_step": "6k_stepI", "k_step_tb2": "10k_step_tb2I"}
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+_BUNDLE_MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
+_GFX950 = b"hipv4-amdgcn-amd-amdhsa--gfx950"
 
 
-def kernel_source_sha(family="k_step"):
+def _elf_sections(d):
+    """{name: (file offset, size, address)} of an ELF64 little-endian image."""
+    shoff, = struct.unpack_from("<Q", d, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", d, 0x3A)
+    hdrs = []
+    for i in range(shnum):
+        name, _, _, addr, off, size = struct.unpack_from("<IIQQQQ", d, shoff + i * shentsize)
+        hdrs.append((name, off, size, addr))
+    stroff = hdrs[shstrndx][1]
+    out = {}
+    for i, (name, off, size, addr) in enumerate(hdrs):
+        end = d.index(b"\0", stroff + name)
+        out[d[stroff + name:end].decode()] = (off, size, addr, i)
+    return out
+
+
+def gfx950_code_objects(lib_path=LIB_PATH):
+    """(file offset, bytes) of the gfx950 code objects inside a HIP shared
+    library: its .hip_fatbin section holds one clang offload bundle per
+    translation unit (magic string, entry count, then offset / size / target
+    triple of each entry)."""
+    d = open(lib_path, "rb").read()
+    base, size, _, _ = _elf_sections(d)[".hip_fatbin"]
+    fat = d[base:base + size]
+    objs, pos = [], fat.find(_BUNDLE_MAGIC)
+    while pos >= 0:
+        n, = struct.unpack_from("<Q", fat, pos + len(_BUNDLE_MAGIC))
+        q, end = pos + len(_BUNDLE_MAGIC) + 8, pos
+        for _ in range(n):
+            eoff, esize, tlen = struct.unpack_from("<QQQ", fat, q)
+            triple = fat[q + 24:q + 24 + tlen]
+            q += 24 + tlen
+            end = max(end, pos + eoff + esize)
+            if triple == _GFX950 and esize:
+                obj = fat[pos + eoff:pos + eoff + esize]
+                if obj[:4] != b"\x7fELF":
+                    raise ValueError("compressed or unknown code object in the offload bundle")
+                objs.append((base + pos + eoff, obj))
+        pos = fat.find(_BUNDLE_MAGIC, end)
+    return objs
+
+
+def kernel_symbols(family="k_step", lib_path=LIB_PATH):
+    """(mangled name, file offset in the library, size) of the machine code and
+    kernel descriptor of every instantiation of a step-kernel family."""
+    marker = KERNEL_FAMILIES[family].encode()
+    found = []
+    for obj_off, obj in gfx950_code_objects(lib_path):
+        sec = _elf_sections(obj)
+        by_index = {v[3]: v for v in sec.values()}
+        symoff, symsize, _, _ = sec[".symtab"]
+        stroff = sec[".strtab"][0]
+        for q in range(symoff, symoff + symsize, 24):
+            name, _, _, shndx, value, size = struct.unpack_from("<IBBHQQ", obj, q)
+            nm = obj[stroff + name:obj.index(b"\0", stroff + name)]
+            if marker not in nm or not size or shndx not in by_index:
+                continue
+            s_off, _, s_addr, _ = by_index[shndx]
+            found.append((nm, obj_off + s_off + value - s_addr, size))
+    return sorted(found)
+
+
+def kernel_code_sha(family="k_step", lib_path=LIB_PATH):
+    """sha256[:16] over the gfx950 machine code and kernel descriptors of every
+    instantiation of a step-kernel family in the built library (symbol names and
+    bytes, in name order): a profile taken on this library stays valid while
+    this value is unchanged, whatever else in the library or its headers changes."""
+    syms = kernel_symbols(family, lib_path)
+    if not syms:
+        raise ValueError(f"no {family} kernels in {lib_path}")
+    d = open(lib_path, "rb").read()
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES[family]:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
-    with open(os.path.join(os.path.dirname(HERE), "include", "lbm.h"), "rb") as f:
-        h.update(f.read())
+    for nm, off, size in syms:
+        h.update(nm + b"\0" + d[off:off + size])
     return h.hexdigest()[:16]
 
 
@@ -138,9 +205,8 @@ def main():
     a = ap.parse_args()
     if a.cmd:
         print(f"command: {a.cmd}")
-    for fam in KERNEL_SOURCES:
-        print(f"{fam} sources ({', '.join(KERNEL_SOURCES[fam])}, lbm.h) sha256[:16]: "
-              f"{kernel_source_sha(fam)}")
+    for fam in KERNEL_FAMILIES:
+        print(f"{fam} gfx950 code sha256[:16]: {kernel_code_sha(fam)}")
     if a.trace:
         print("\nkernel trace (durations in us; grid = threads launched)")
         print(f"{'kernel':58s} {'grid':>11s} {'calls':>6s} {'mean':>10s} {'median':>10s} "
@@ -163,7 +229,7 @@ def main():
             print(f"{key:>16s} {fam:>10s} {n:6d} launches {tot / n:10.2f} us")
         if a.durations_out:
             write_table(a.durations_out, {k: (v[0] / v[1], v[1], v[2]) for k, v in per_key.items()},
-                        lambda key, val: f"{key} {kernel_source_sha(val[2])} {val[0]:.3f} "
+                        lambda key, val: f"{key} {kernel_code_sha(val[2])} {val[0]:.3f} "
                                          f"{val[1]} {val[2]}\n", fam_col=4)
     if a.fetch and a.write:
         fb = counters(a.fetch, "FETCH_SIZE")
@@ -242,9 +308,9 @@ def sq_table(d, precision, tb2_n, simds=1024, clock_ghz=2.4):
 
 def write_table(path, per_key, fmt, fam_col):
     """Rewrite a per-lattice table: its comment lines, the earlier entries that
-    were taken on the current sources of their kernel and not measured again now,
-    then the new entries.  Entries of older sources are dropped."""
-    current = {fam: kernel_source_sha(fam) for fam in KERNEL_SOURCES}
+    were taken on the current machine code of their kernel and not measured again
+    now, then the new entries.  Entries of older code are dropped."""
+    current = {fam: kernel_code_sha(fam) for fam in KERNEL_FAMILIES}
     head, keep = [], []
     if os.path.exists(path):
         for ln in open(path):
@@ -263,7 +329,7 @@ def write_table(path, per_key, fmt, fam_col):
 
 def write_traffic(path, per_key):
     write_table(path, per_key,
-                lambda key, v: f"{key} {kernel_source_sha(v[3])} {v[0] / v[2]:.6e} "
+                lambda key, v: f"{key} {kernel_code_sha(v[3])} {v[0] / v[2]:.6e} "
                                f"{v[1] / v[2]:.6e} {v[3]} mean over {v[2]} kernels\n", fam_col=4)
 
 

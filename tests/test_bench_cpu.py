@@ -13,16 +13,16 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_counter_traffic_is_keyed_by_kernel_sources():
+def test_counter_traffic_is_keyed_by_kernel_code():
     sys.path.insert(0, ROOT)
     import bench
-    from paper_2512_23116_amd.rocprof_summary import kernel_source_sha
+    from paper_2512_23116_amd.rocprof_summary import kernel_code_sha
     path = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_forced_hit_100_800.txt")
     rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
     assert rows, "no counter rows"
     for key, sha, fetch, write, fam, *_ in rows:
         got = bench.counter_traffic(key, fam)
-        if sha == kernel_source_sha(fam):
+        if sha == kernel_code_sha(fam):
             assert got == float(fetch) + float(write)
         else:
             assert got is None
@@ -48,3 +48,43 @@ def test_precision_errors_compare_common_snapshots_after_the_start():
     assert e["spectrum_rel_err_last"]["k<=8"] == 0.0
     assert abs(e["spectrum_rel_err_last"]["k<=32"] - 0.5) < 1e-12
     assert set(e["spectrum_rel_err_last"]) == {"k<=8", "k<=32", "k<=10"}
+
+
+def test_kernel_code_sha_follows_the_kernel_machine_code(tmp_path, monkeypatch):
+    """The profile-table key hashes each step-kernel family's gfx950 code and
+    descriptors: it sees every instantiation, changes when one byte of that code
+    changes, and stays put when only another kernel's code changes."""
+    import shutil
+    from paper_2512_23116_amd import lbm
+    from paper_2512_23116_amd import rocprof_summary as R
+    if not os.path.exists(lbm.LIB_PATH):
+        raise AssertionError("liblbm.so is not built (run __graft_entry__.build())")
+    syms = R.kernel_symbols("k_step")
+    names = [nm.decode() for nm, _, _ in syms]
+    for codec in ("CdF64", "CdF32", "CdF16", "CdBF16"):
+        for pat in (0, 1, 2):
+            mangled = f"_ZN3lbm6k_stepINS_{len(codec)}{codec}ELi{pat}ELi0EEEvNS_11LatticeArgsE"
+            assert mangled in names and mangled + ".kd" in names
+    assert len(R.kernel_symbols("k_step_tb2")) >= 4
+    base = {f: R.kernel_code_sha(f) for f in R.KERNEL_FAMILIES}
+    assert base == {f: R.kernel_code_sha(f) for f in R.KERNEL_FAMILIES}
+
+    def flipped(off):
+        p = tmp_path / f"lib_{off}.so"
+        shutil.copy(lbm.LIB_PATH, p)
+        with open(p, "r+b") as fh:
+            fh.seek(off)
+            b = fh.read(1)
+            fh.seek(off)
+            fh.write(bytes([b[0] ^ 0x01]))
+        return str(p)
+
+    _, off, size = next(s for s in syms if not s[0].endswith(b".kd"))
+    lib1 = flipped(off + size // 2)
+    assert R.kernel_code_sha("k_step", lib1) != base["k_step"]
+    assert R.kernel_code_sha("k_step_tb2", lib1) == base["k_step_tb2"]
+    monkeypatch.setitem(R.KERNEL_FAMILIES, "k_stream", "8k_streamI")
+    _, off, size = R.kernel_symbols("k_stream")[0]
+    lib2 = flipped(off + size // 2)
+    assert {f: R.kernel_code_sha(f, lib2) for f in ("k_step", "k_step_tb2")} == \
+        {f: base[f] for f in ("k_step", "k_step_tb2")}
