@@ -4,7 +4,11 @@
 // single-step kernel runs at the ceiling of that access pattern.  This kernel
 // keeps the intermediate time level on chip instead: a workgroup owns a
 // 62 x 14 tile of (x, y) columns plus a one-cell halo (64 x 16 = 1024
-// threads) and marches along z through a chunk of planes.
+// threads) and marches along z through a chunk of planes.  Which (tile,
+// chunk) a workgroup takes is planned on the host once per lattice shape
+// (lbm_tb2_plan.hpp): each XCD owns a contiguous range of tiles and runs
+// their chunks in order, the long ones first and one short chunk per tile
+// last, so that its CUs run out of work at nearly the same time.
 //   phase 1  each of the 1024 columns pulls f(t) of plane z+1 from A
 //            (eq. mrt_dns_guo, periodic) and collides; of the post-collision
 //            values it keeps in LDS exactly what phase 2 will pull: the 5
@@ -19,14 +23,21 @@
 // overlap with its arithmetic.  HBM traffic per two cell updates: A is read
 // once per extended column (1024 / 868 of the interior, plus 2 planes per
 // chunk) and B is written once, instead of two full reads and writes.
-// Per cell the arithmetic is the single-step collision; for 16-bit storage
-// the LDS buffers hold the intermediate level in the storage format, so the
-// result matches two single steps.
+// Per cell the arithmetic is the single-step collision, and for 16-bit
+// storage the LDS buffers hold the intermediate level in the storage format:
+// the result is that of two single steps up to the rounding of the FP32
+// collision (the compilers of the two kernels may fuse its multiply-adds
+// differently).  It does not depend on the work plan.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <map>
+#include <mutex>
+
 #include "lbm_device.hpp"
+#include "lbm_tb2_plan.hpp"
 
 namespace lbm {
-
-constexpr int TB_EX = 64, TB_TX = TB_EX - 2;
 
 // Position of direction i within its class of c_z (-1: 5, 0: 9, +1: 5).
 __host__ __device__ constexpr int zclass_index(int i) {
@@ -37,7 +48,8 @@ __host__ __device__ constexpr int zclass_index(int i) {
 
 struct TB2Args {
     LatticeArgs L;
-    uint32_t tiles_x, tiles_y, zchunk, nblocks;
+    uint32_t tiles_x, tiles_y;
+    Tb2Work W;
 };
 
 __device__ __forceinline__ uint32_t wrap_add(uint32_t base, int d, uint32_t n) {
@@ -69,14 +81,11 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     __shared__ R xbuf[TB_EX][4];         // x harmonics of the tile columns
 
     const LatticeArgs& L = A.L;
-    // one contiguous range of tiles per XCD whenever a block order is asked for
-    const uint32_t b = block_order(blockIdx.x, gridDim.x, L.xcd_remap ? 1 : 0);
-    const uint32_t tile_x = b % A.tiles_x;
-    const uint32_t rest = b / A.tiles_x;
-    const uint32_t tile_y = rest % A.tiles_y;
-    const uint32_t zc = rest / A.tiles_y;
-    const uint32_t X0 = tile_x * TB_TX, Y0 = tile_y * TB_TY, Z0 = zc * A.zchunk;
-    const int nzc = (int)min(A.zchunk, L.nz - Z0);        // output planes of this chunk
+    uint32_t tile, Z0, nplanes;
+    if (!tb2_item(A.W, L.nz, blockIdx.x, tile, Z0, nplanes)) return;   // padding: all leave
+    const uint32_t tile_x = tile % A.tiles_x, tile_y = tile / A.tiles_x;
+    const uint32_t X0 = tile_x * TB_TX, Y0 = tile_y * TB_TY;
+    const int nzc = (int)nplanes;                                 // output planes of this chunk
 
     const int t = threadIdx.x;
     const int ex = t & (TB_EX - 1), ey = t / TB_EX;
@@ -93,12 +102,12 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
     const uint64_t pbytes = L.plane * (uint64_t)sizeof(T);
     const PlaneStride src{(char*)L.a, pbytes}, dst{(char*)L.b, pbytes};
     const CollideConst<R>& k = collide_const<R>(L);
-    // FP16: the array bases are made opaque inside the loop, so the compiler
-    // recomputes the 38 plane bases per use instead of keeping them live across
-    // it and spilling scalar registers to VGPR lanes (+1.4 % at 800^3; BF16 and
-    // FP32 measured 1 % / 0 % slower that way and keep the hoisted bases)
+    // 16-bit storage: the array bases are made opaque inside the loop, so the
+    // compiler recomputes the 38 plane bases per use instead of keeping them
+    // live across it and spilling scalar registers to VGPR lanes (at 800^3:
+    // FP16 +1.4 %, BF16 +13 %; FP32 measured no gain and keeps hoisted bases)
     auto opaque_base = [&](char* p) -> char* {
-        if constexpr (std::is_same_v<Cd, CdF16>) asm volatile("" : "+s"(p));
+        if constexpr (k16) asm volatile("" : "+s"(p));
         return p;
     };
     auto to_lds = [&](R v) -> LT {
@@ -244,22 +253,54 @@ __global__ __launch_bounds__(TB_EX * TB_EY) void k_step_tb2(TB2Args A) {
 
 bool tb2_supported(int precision) { return precision != LBM_FP64; }
 
+namespace {
+
+// Compute units of the current device, asked once per device.
+uint32_t compute_units() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return (uint32_t)n;
+}
+
+// Plans are made once per (shape, grouping, CU count) and kept.
+const Tb2Plan& plan_for(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t tiles_x,
+                        uint32_t tiles_y, uint32_t groups) {
+    static std::mutex mu;
+    static std::map<std::array<uint32_t, 5>, Tb2Plan> plans;
+    const uint32_t cus = compute_units();
+    const std::array<uint32_t, 5> key{nx, ny, nz, groups, cus};
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = plans.find(key);
+    if (it == plans.end())
+        it = plans.emplace(key, make_plan(nx, ny, nz, tiles_x, tiles_y, groups, cus)).first;
+    return it->second;
+}
+
+}  // namespace
+
 hipError_t launch_step_tb2(int precision, const LatticeArgs& L, hipStream_t s) {
-    // 64 x 16 extended tiles: one 1024-thread workgroup and 152-155 KB of LDS per CU.
+    // 64 x 16 extended tiles: one 1024-thread workgroup and 117-155 KB of LDS per CU.
     // (64 x 8 tiles, two workgroups per CU, measured 25 % slower at 800^3.)
-    constexpr int EY = 16;
+    constexpr int EY = kTbEY;
     TB2Args A;
     A.L = L;
     A.tiles_x = (L.nx + TB_TX - 1) / TB_TX;
     A.tiles_y = (L.ny + (EY - 2) - 1) / (EY - 2);
-    // enough workgroups to fill 256 CUs several times over, but long z chunks
-    const uint32_t tiles = A.tiles_x * A.tiles_y;
-    uint32_t chunks = (2048 + tiles - 1) / tiles;
-    chunks = std::max(1u, std::min(chunks, std::max(1u, L.nz / 16)));
-    A.zchunk = (L.nz + chunks - 1) / chunks;
-    chunks = (L.nz + A.zchunk - 1) / A.zchunk;
-    A.nblocks = tiles * chunks;
-    const dim3 grid(A.nblocks), block(TB_EX * EY);
+    // one tile range per XCD whenever a block order is asked for
+    const uint32_t groups = L.xcd_remap ? 8u : 1u;
+    const Tb2Plan& P = plan_for(L.nx, L.ny, L.nz, A.tiles_x, A.tiles_y, groups);
+    A.W = P.w;
+    const uint64_t nblocks = (uint64_t)P.w.groups * P.per_group;
+    if (nblocks == 0 || nblocks > 0x7fffffffull) return hipErrorInvalidValue;
+    const dim3 grid((uint32_t)nblocks), block(TB_EX * EY);
     switch (precision) {
         case LBM_FP32: hipLaunchKernelGGL((k_step_tb2<CdF32, EY>), grid, block, 0, s, A); break;
         case LBM_FP16_DEV: hipLaunchKernelGGL((k_step_tb2<CdF16, EY>), grid, block, 0, s, A); break;
