@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -20,66 +21,120 @@ namespace lbm {
 
 constexpr int kAnaBlocks = 1024;
 
-// Per-block partial sums of 1/2 w |c|^2 / n^2 over the shells 0..kmax of one
-// R2C output c[nz][ny][nx/2+1]; w = 2 for the kx > 0 modes that stand for a
-// conjugate pair.
+// The binning kernels below sum in a fixed order, so that a spectrum is the
+// same bit for bit on every call: each wave of a block takes whole rows (fixed
+// ky, kz) of the R2C output c[nz][ny][nx/2+1] in turn, 64 values of kx at a
+// time, and adds into a histogram of its own in LDS in program order; the block
+// then adds its waves' histograms in wave order (and k_sum_rows its blocks'
+// partial sums in block order).  A block has 1 to 4 waves, as many as let their
+// histograms fit 64 KB of LDS.
+
+// Per-block partial sums of 1/2 w |c|^2 / n^2 over the shells 0..kmax; w = 2 for
+// the kx > 0 modes that stand for a conjugate pair.  Along a row the shell index
+// never decreases with kx, so equal shells are contiguous runs of lanes: a
+// segmented scan over the 64 lanes sums each run, and the run's last lane adds
+// that sum to the wave's histogram (one lane per shell, no two lanes on one bin).
 __global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c, uint32_t nx,
                                                    uint32_t ny, uint32_t nz, int kmax,
                                                    double inv_n2, double* partials) {
-    extern __shared__ double hist[];
-    for (int k = threadIdx.x; k <= kmax; k += 256) hist[k] = 0.0;
+    extern __shared__ double hist[];   // [waves][kmax + 1]
+    const int nb = kmax + 1, waves = (int)(blockDim.x >> 6);
+    for (int k = threadIdx.x; k < waves * nb; k += blockDim.x) hist[k] = 0.0;
     __syncthreads();
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    double* wh = hist + wave * nb;
     const uint32_t hx = nx / 2 + 1;
-    const uint64_t total = (uint64_t)hx * ny * nz;
-    for (uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x; m < total;
-         m += (uint64_t)gridDim.x * 256) {
-        const uint32_t ix = (uint32_t)(m % hx);
-        const uint64_t r = m / hx;
-        const uint32_t iy = (uint32_t)(r % ny), iz = (uint32_t)(r / ny);
-        const double kx = ix;
+    const uint64_t rows = (uint64_t)ny * nz;
+    for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows;
+         row += (uint64_t)gridDim.x * waves) {
+        const uint32_t iy = (uint32_t)(row % ny), iz = (uint32_t)(row / ny);
         const double ky = iy <= ny / 2 ? (double)iy : (double)iy - ny;
         const double kz = iz <= nz / 2 ? (double)iz : (double)iz - nz;
-        const int shell = (int)floor(sqrt(kx * kx + ky * ky + kz * kz) + 0.5);
-        if (shell > kmax) continue;
-        const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
-        const hipfftDoubleComplex v = c[m];
-        atomicAdd(&hist[shell], 0.5 * w * (v.x * v.x + v.y * v.y) * inv_n2);
+        const double kyz2 = ky * ky + kz * kz;
+        const hipfftDoubleComplex* crow = c + row * hx;
+        for (uint32_t x0 = 0; x0 < hx; x0 += 64) {
+            const uint32_t ix = x0 + (uint32_t)lane;
+            const bool in = ix < hx;
+            const double kx = (double)ix;
+            const int shell = in ? (int)floor(sqrt(kx * kx + kyz2) + 0.5) : INT_MAX;
+            // the row's shells only grow: once lane 0 is past kmax, so is the rest
+            if (__shfl(shell, 0, 64) > kmax) break;
+            double v = 0.0;
+            if (in && shell <= kmax) {
+                const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
+                const hipfftDoubleComplex z = crow[ix];
+                v = 0.5 * w * (z.x * z.x + z.y * z.y) * inv_n2;
+            }
+            for (int d = 1; d < 64; d <<= 1) {   // segmented inclusive scan over the runs
+                const double vu = __shfl_up(v, d, 64);
+                const int su = __shfl_up(shell, d, 64);
+                if (lane >= d && su == shell) v += vu;
+            }
+            const int next = __shfl_down(shell, 1, 64);
+            if (in && shell <= kmax && (lane == 63 || next != shell)) wh[shell] += v;
+        }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k <= kmax; k += 256)
-        partials[(uint64_t)blockIdx.x * (kmax + 1) + k] = hist[k];
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        double s = hist[k];
+        for (int w = 1; w < waves; ++w) s += hist[w * nb + k];
+        partials[(uint64_t)blockIdx.x * nb + k] = s;
+    }
 }
 
-// Per-block partial sums of w |c|^2 / n^2 of one R2C output c[nz][ny][nx/2+1]
-// binned by |k_x|, |k_y| and |k_z| separately (0..kmax each):
-// partials[block][axis][k], axis 0, 1, 2 = x, y, z.  w = 2 for the kx > 0 modes
-// that stand for a conjugate pair (both members have the same |k_a|).
+// Per-block partial sums of w |c|^2 / n^2 binned by |k_x|, |k_y| and |k_z|
+// separately (0..kmax each): partials[block][axis][k], axis 0, 1, 2 = x, y, z.
+// w = 2 for the kx > 0 modes that stand for a conjugate pair (both members
+// have the same |k_a|).  In a row every lane has its own |k_x| bin, and the
+// whole row shares one |k_y| and one |k_z| bin: lane 0 adds the row's total,
+// folded chunk by chunk over a fixed butterfly.
 __global__ __launch_bounds__(256) void k_axis_bin(const hipfftDoubleComplex* c, uint32_t nx,
                                                   uint32_t ny, uint32_t nz, int kmax,
                                                   double inv_n2, double* partials) {
-    extern __shared__ double hist[];
-    const int nb = 3 * (kmax + 1);
-    for (int k = threadIdx.x; k < nb; k += 256) hist[k] = 0.0;
+    extern __shared__ double hist[];   // [waves][3][kmax + 1]
+    const int nb = 3 * (kmax + 1), waves = (int)(blockDim.x >> 6);
+    for (int k = threadIdx.x; k < waves * nb; k += blockDim.x) hist[k] = 0.0;
     __syncthreads();
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    double* wh = hist + wave * nb;
     const uint32_t hx = nx / 2 + 1;
-    const uint64_t total = (uint64_t)hx * ny * nz;
-    for (uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x; m < total;
-         m += (uint64_t)gridDim.x * 256) {
-        const uint32_t ix = (uint32_t)(m % hx);
-        const uint64_t r = m / hx;
-        const uint32_t iy = (uint32_t)(r % ny), iz = (uint32_t)(r / ny);
-        const int ax = (int)ix;
+    const uint64_t rows = (uint64_t)ny * nz;
+    for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows;
+         row += (uint64_t)gridDim.x * waves) {
+        const uint32_t iy = (uint32_t)(row % ny), iz = (uint32_t)(row / ny);
         const int ay = (int)(iy <= ny / 2 ? iy : ny - iy);
         const int az = (int)(iz <= nz / 2 ? iz : nz - iz);
-        const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
-        const hipfftDoubleComplex v = c[m];
-        const double p = w * (v.x * v.x + v.y * v.y) * inv_n2;
-        if (ax <= kmax) atomicAdd(&hist[ax], p);
-        if (ay <= kmax) atomicAdd(&hist[kmax + 1 + ay], p);
-        if (az <= kmax) atomicAdd(&hist[2 * (kmax + 1) + az], p);
+        const hipfftDoubleComplex* crow = c + row * hx;
+        double total = 0.0;
+        for (uint32_t x0 = 0; x0 < hx; x0 += 64) {
+            const uint32_t ix = x0 + (uint32_t)lane;
+            double p = 0.0;
+            if (ix < hx) {
+                const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
+                const hipfftDoubleComplex z = crow[ix];
+                p = w * (z.x * z.x + z.y * z.y) * inv_n2;
+                if ((int)ix <= kmax) wh[ix] += p;
+            }
+            for (int d = 32; d > 0; d >>= 1) p += __shfl_xor(p, d, 64);
+            total += p;
+        }
+        if (lane == 0) {
+            if (ay <= kmax) wh[kmax + 1 + ay] += total;
+            if (az <= kmax) wh[2 * (kmax + 1) + az] += total;
+        }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nb; k += 256) partials[(uint64_t)blockIdx.x * nb + k] = hist[k];
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        double s = hist[k];
+        for (int w = 1; w < waves; ++w) s += hist[w * nb + k];
+        partials[(uint64_t)blockIdx.x * nb + k] = s;
+    }
+}
+
+// Threads per block of a binning kernel whose waves each keep `hist_bytes` of
+// histogram: up to 4 waves within 64 KB of LDS.
+static int bin_threads(size_t hist_bytes) {
+    return 64 * (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / hist_bytes));
 }
 
 // out[g][j] (+)= scale * sum over rows b of partials[g][b][j], one block per
@@ -313,10 +368,11 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     hipfftResult fr = HIPFFT_SUCCESS;
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
+    const int bt = bin_threads(shm);
     for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
         fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
         if (fr != HIPFFT_SUCCESS) break;
-        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), h->stream,
                            (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
         hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
                            (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
@@ -373,11 +429,12 @@ lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z) {
     if (e != hipSuccess) return hip_err(h, e, "snapshot (state reads)");
     const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
+    const int bt = bin_threads(shm);
     hipfftResult fr = HIPFFT_SUCCESS;
     for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
         fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(a.u + (size_t)c * nc), a.c);
         if (fr != HIPFFT_SUCCESS) break;
-        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(256), shm, h->stream,
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), h->stream,
                            (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
         hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
                            (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
@@ -456,9 +513,11 @@ lbm_status lbm_spectra_1d(lbm_handle* h, int32_t kmax, double* E, double* ic) {
     for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
         fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
         if (fr != HIPFFT_SUCCESS) break;
-        hipLaunchKernelGGL(k_axis_bin, dim3(kAnaBlocks), dim3(256), (size_t)cols * sizeof(double),
-                           h->stream, (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax,
-                           inv_n2, a.part);
+        const size_t hb = (size_t)cols * sizeof(double);
+        const int bt = bin_threads(hb);
+        hipLaunchKernelGGL(k_axis_bin, dim3(kAnaBlocks), dim3(bt), hb * (bt / 64), h->stream,
+                           (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2,
+                           a.part);
         hipLaunchKernelGGL(k_sum_rows, dim3(cols), dim3(256), 0, h->stream, (const double*)a.part,
                            kAnaBlocks, cols, 1.0, 0, a.out + (size_t)c * cols);
     }

@@ -202,3 +202,30 @@ def test_theta_histogram_matches_oracle(lbm, shape, precision, streaming):
         with pytest.raises(lbm.LbmError):
             lat.theta_histogram(*bad)
     lat.close()
+
+
+@pytest.mark.parametrize("shape,precision", [((36, 48, 40), "fp64"), ((100, 100, 100), "fp32"),
+                                             ((130, 7, 5), "fp64")])
+def test_spectra_are_bitwise_reproducible(lbm, shape, precision):
+    """The binning sums in a fixed order: repeated spectra, the snapshot's
+    spectrum and a spectrum cut at a smaller kmax agree bit for bit, and a kmax
+    large enough to give the binning blocks fewer waves (another summation order)
+    agrees to rounding."""
+    lat = lbm.Lattice(shape, 0.52, 0.13, forced_modes(F0=3e-5, seed=6), precision=precision,
+                      smag_form=1)
+    lat.init(lbm.LBM_INIT_NOISE, 0.03, 11)
+    lat.step(20)
+    kmax = max(shape) // 2 + 3
+    E = [lat.spectrum(kmax) for _ in range(3)]
+    assert all(np.array_equal(E[0], e) for e in E[1:])
+    lat.snapshot_begin(kmax, 0)
+    _, E_snap, _ = lat.snapshot_end()
+    assert np.array_equal(E_snap, E[0])
+    E_cut = lat.spectrum(5)
+    assert np.array_equal(E_cut, E[0][:6])
+    E_big = lat.spectrum(3000)            # 24 KB of histogram per wave: 2 waves per block
+    np.testing.assert_allclose(E_big[:kmax + 1], E[0], rtol=1e-13, atol=1e-300)
+    assert not E_big[int(np.ceil(np.sqrt(3) * max(shape) / 2)) + 1:].any()
+    S1 = [lat.spectra_1d(kmax, with_ic=False) for _ in range(2)]
+    assert np.array_equal(S1[0][0], S1[1][0])
+    lat.close()
