@@ -110,7 +110,9 @@ typedef struct {
                                 FP32/FP16/BF16; steps_per_graph a multiple of
                                 4 or 0): the intermediate level stays in LDS,
                                 halving HBM traffic per step at ~19% more
-                                arithmetic.  Same results as single steps.    */
+                                arithmetic.  Results equal single steps up to
+                                the rounding of the FP32 collision, and do not
+                                depend on how a launch splits the work.        */
     int32_t tau_mode;        /* which relaxation rate enters the strain
                                 estimate of App. B.1 eq. yu_strain:
                                 0: s_1 = s_e and s_9 = 1/tau0 (explicit,
