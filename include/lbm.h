@@ -181,6 +181,17 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_handle** out);
  * `kind` (lbm_init_kind) and amplitude A; resets the step count to 0. */
 lbm_status lbm_init_seeded(lbm_handle* h, int32_t kind, double amplitude, uint64_t seed);
 
+/* Set f(x, 0) = f_eq(rho(x), u(x)) (App. A eq. feq) from fields the caller
+ * holds in device memory of the lattice's device: u[a * ncells + c] (a = x, y,
+ * z; c = x + nx (y + ny z)), FP64 lattice units, and rho[c], or rho = NULL for
+ * rho0 everywhere.  Starts a run from a given flow, e.g. one interpolated from
+ * a coarser lattice.  Resets the step count to 0.  The kernel reads u and rho on
+ * the lattice's stream after the call returns: the caller orders their writes
+ * before it and keeps them alive until the stream has passed it (lbm_synchronize).
+ * Errors: INVALID_ARG (u NULL, or u / rho not device memory of that device),
+ * DEVICE. */
+lbm_status lbm_init_velocity(lbm_handle* h, const double* u, const double* rho);
+
 /* Advance n >= 0 steps of eq. mrt_les_guo, asynchronously on the stream.
  * Full graphs of steps_per_graph steps are replayed, the rest is launched. */
 lbm_status lbm_step(lbm_handle* h, int64_t n);

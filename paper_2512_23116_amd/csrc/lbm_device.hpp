@@ -111,6 +111,15 @@ __device__ __forceinline__ int32_t off_minus_rt(int i, const Nbr& n) {
     return o;
 }
 
+// Element index (slot * plane + cell) of the canonical f_i(x) for a runtime
+// direction and pattern (set-up and observation kernels).
+__device__ __forceinline__ uint64_t canon_index(int pat, int i, uint32_t cell, const Nbr& nb,
+                                                uint64_t plane) {
+    const int slot = (pat == PAT_AA_ODD) ? opp_of(i) : i;
+    const uint32_t c = (pat == PAT_AA_EVEN) ? cell : cell + (uint32_t)off_minus_rt(i, nb);
+    return (uint64_t)slot * plane + c;
+}
+
 // Block of cells of this workgroup in the XCD-aware order of L.xcd_remap.
 __device__ __forceinline__ uint32_t block_id(const LatticeArgs& L) {
     return block_order(blockIdx.x, gridDim.x, L.xcd_remap);

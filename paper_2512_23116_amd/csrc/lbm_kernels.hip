@@ -235,14 +235,6 @@ __global__ __launch_bounds__(256) void k_theta_hist(LatticeArgs L, double lo, do
         if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
 }
 
-// Slot and cell of f_i(x) for a runtime direction.
-__device__ __forceinline__ uint64_t canon_index(int pat, int i, uint32_t cell, const Nbr& nb,
-                                                uint64_t plane) {
-    const int slot = (pat == PAT_AA_ODD) ? opp_of(i) : i;
-    const uint32_t c = (pat == PAT_AA_EVEN) ? cell : cell + (uint32_t)off_minus_rt(i, nb);
-    return (uint64_t)slot * plane + c;
-}
-
 template <class Cd>
 __global__ __launch_bounds__(256) void k_gather_plane(LatticeArgs L, int pat, int i, double* out) {
     using T = typename Cd::T;

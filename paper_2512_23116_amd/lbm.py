@@ -28,7 +28,8 @@ STREAMING = {"aa": LBM_STREAM_AA, "ab": LBM_STREAM_AB}
 
 # C-ABI entry points every build must export (checked by the CPU tests).
 EXPORTS = (
-    "lbm_config_default", "lbm_required_bytes", "lbm_create", "lbm_init_seeded", "lbm_step",
+    "lbm_config_default", "lbm_required_bytes", "lbm_create", "lbm_init_seeded",
+    "lbm_init_velocity", "lbm_step",
     "lbm_stream_only",
     "lbm_moments", "lbm_kt_stats", "lbm_kt_field", "lbm_kt_slice", "lbm_get_populations",
     "lbm_set_populations", "lbm_sample_populations", "lbm_synchronize", "lbm_set_stream",
@@ -137,6 +138,7 @@ def lib():
         "lbm_required_bytes": (ctypes.c_size_t, [ctypes.POINTER(lbm_config)]),
         "lbm_create": (ctypes.c_int, [ctypes.POINTER(lbm_config), ctypes.POINTER(H)]),
         "lbm_init_seeded": (ctypes.c_int, [H, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64]),
+        "lbm_init_velocity": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_step": (ctypes.c_int, [H, ctypes.c_int64]),
         "lbm_stream_only": (ctypes.c_int, [H, ctypes.c_int64]),
         "lbm_moments": (ctypes.c_int, [H, dp, dp]),
@@ -222,6 +224,12 @@ def lbm_create(cfg):
 
 def lbm_init_seeded(h, kind, amplitude, seed):
     _check(lib().lbm_init_seeded(h, kind, amplitude, seed & ((1 << 64) - 1)), h)
+
+
+def lbm_init_velocity(h, u_ptr, rho_ptr=None):
+    """u_ptr, rho_ptr: device addresses (int) of FP64 arrays, rho_ptr may be None."""
+    _check(lib().lbm_init_velocity(h, ctypes.c_void_p(u_ptr),
+                                   None if rho_ptr is None else ctypes.c_void_p(rho_ptr)), h)
 
 
 def lbm_step(h, n):
@@ -453,6 +461,28 @@ class Lattice:
     def init(self, kind, amp, seed=0):
         """lbm_init_seeded: equilibrium of an LBM_INIT_* velocity field; steps = 0."""
         lbm_init_seeded(self.handle, kind, amp, seed)
+        return self
+
+    def init_velocity(self, u, rho=None):
+        """lbm_init_velocity: equilibrium of a velocity (and density) field held in
+        torch CUDA float64 tensors of shape (3, nz, ny, nx) (and (nz, ny, nx));
+        steps = 0.  Ordered after the work queued on torch's current stream, and
+        waits for the lattice's stream before it returns, so the tensors may be
+        freed afterwards."""
+        import torch
+        nz, ny, nx = self.shape
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64
+                and tuple(u.shape) == (3, nz, ny, nx)):
+            raise ValueError("u must be a CUDA float64 tensor of shape (3, nz, ny, nx)")
+        if rho is not None and not (isinstance(rho, torch.Tensor) and rho.is_cuda
+                                    and rho.dtype == torch.float64
+                                    and tuple(rho.shape) == (nz, ny, nx)):
+            raise ValueError("rho must be a CUDA float64 tensor of shape (nz, ny, nx)")
+        u = u.contiguous()
+        rho = None if rho is None else rho.contiguous()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        lbm_init_velocity(self.handle, u.data_ptr(), None if rho is None else rho.data_ptr())
+        self.sync()
         return self
 
     def step(self, n=1):

@@ -1,6 +1,7 @@
 """The study modules run end to end on small settings."""
 import math
 
+import numpy as np
 import pytest
 
 from tests.helpers import gpu_available
@@ -124,3 +125,41 @@ def test_c_sweep_study_small():
         assert all(math.isfinite(v) and v >= 0 for v in r["E"])
         assert set(r["ratio_to_dns"]) == {2, 4, 8, 16}
     assert res["les"][1]["E"][16] < res["les"][0]["E"][16]
+
+
+def test_refined_start_carries_the_coarse_flow_onto_the_fine_lattice():
+    """The refined iso-Reynolds start on a small pair: the fine lattice starts
+    from the spectral interpolation of the coarse LES's velocity (run here a
+    second time, identically), stands for the coarse run's physical time, and
+    its step count starts at 0."""
+    import torch
+    from paper_2512_23116_amd import lbm, params
+    from paper_2512_23116_amd.inputs import paper_modes
+    from paper_2512_23116_amd.studies import iso_re_pair as P
+    N, Re, t_start = 32, 2.0e3, 2
+    # unforced, so that its moments give j / rho, the velocity it was started from
+    # (with forcing they add the half-force shift F / 2 rho)
+    fine = lbm.Lattice((N, N, N), params.tau0_from_re(N, Re), 0.0, precision="fp32",
+                       streaming="ab", smag_form=1, temporal_block=2)
+    step0 = P.refined_start(Re, 0.13, t_start, log=lambda m: None)(fine)
+    assert step0 == t_start * P.T0 and fine.steps == 0
+    Nc = N // 2
+    coarse = lbm.Lattice((Nc, Nc, Nc), params.tau0_from_re(Nc, Re), 0.13,
+                         paper_modes(params.forcing_amplitude(Nc)), precision="fp32",
+                         streaming="ab", smag_form=1, temporal_block=2)
+    coarse.init(lbm.LBM_INIT_TGV3D, params.U0)
+    coarse.step(t_start * P.T0 * Nc // N)
+    rho_c, u_c = coarse.moments()
+    coarse.close()
+    u_ref = np.stack([P.spectral_upsample(u_c[a], N) for a in range(3)])
+    rho_f, u_f = fine.moments()
+    err = np.abs(u_f - u_ref).max() / np.abs(u_ref).max()
+    print(f"refined start: velocity vs the interpolated coarse flow {err:.2e}", flush=True)
+    assert err <= 1e-5
+    assert np.abs(rho_f - P.spectral_upsample(rho_c, N)).max() <= 1e-6
+    # at the coarse points the two differ by the coarse Nyquist modes only
+    assert np.abs(u_f[:, ::2, ::2, ::2] - u_c).max() <= 0.1 * np.abs(u_c).max()
+    fine.step(4)
+    assert np.isfinite(fine.populations()).all()
+    fine.close()
+    torch.cuda.empty_cache()
