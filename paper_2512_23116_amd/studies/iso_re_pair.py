@@ -127,6 +127,7 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
     scales = []
     th = []
     n = 0
+    last_log = time.time()
     for step in range(t_start * t0, t_end * t0 + 1, every):
         if step > step0 + lat.steps:
             lat.step(step - step0 - lat.steps)
@@ -138,8 +139,9 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
             st = lat.stats()
             th.append((st["theta_mean"], st["theta_var"], st["theta_min"], st["theta_max"]))
         n += 1
-        if n % 25 == 0:
+        if n % 25 == 0 or time.time() - last_log > 30:
             log(f"{kind} {N}^3: window t/t0 = {step / t0:g}, {time.time() - tic:.0f} s")
+            last_log = time.time()
     lat.close()
     E /= n
     S /= n
