@@ -134,6 +134,7 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
         E += lat.spectrum(kmax)
         S += lat.structure_functions(rs)
         tb_ = lat.turbulence()
+        tb_["t"] = step / t0
         scales.append(tb_)
         if C > 0:
             st = lat.stats()
@@ -162,7 +163,10 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
                # E(kappa) = shell energy / shell width 2 pi / N
                E_kolmogorov=[float(v) for v in E[1:] * N / (2 * np.pi) / (eps * nu0 ** 5) ** 0.25],
                r_over_eta=[float(r / eta) for r in rs],
-               F4=[float(v) for v in S[:, 3] / S[:, 0] ** 2], wall_s=time.time() - tic)
+               F4=[float(v) for v in S[:, 3] / S[:, 0] ** 2], wall_s=time.time() - tic,
+               # per snapshot: t/t0, resolved dissipation / injected power, Re_lambda
+               series=[[s["t"], s["eps_spec"] / s["injection"] if s["injection"] else None,
+                        s["re_lambda"]] for s in scales])
     lo, hi = max(2, int(3 * N / 100)), max(6, int(12 * N / 100))
     sel = [i for i, r in enumerate(rs) if lo <= r <= hi]
     x = np.log(S[sel, 2])
