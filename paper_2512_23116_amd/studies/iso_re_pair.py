@@ -11,8 +11,8 @@ Two ways to run it:
   (LES), grid ratio 8, Re = 1e4, both from the Taylor-Green start;
 - ``--refine``: the paper's 800^3 / 100^3 pair at Re = 2e4.  One session cannot
   run the 800^3 DNS from t = 0 to the window (2e5 steps to t/t0 = 200), so it
-  starts from a developed flow: an LES of the same Re on 400^3 (C = 0.13) runs
-  for the same physical time (1e5 of its steps, the lattice velocity being the
+  starts from a developed flow: a run of the same Re on 400^3 (an LES with
+  C = 0.13, or with --coarse-C 0 a DNS) runs for the same physical time (1e5 of its steps, the lattice velocity being the
   same), its velocity and density are interpolated onto 800^3 by their Fourier
   series (spectral_upsample) and the DNS starts from their equilibrium
   (lbm_init_velocity) at t/t0 = t_start, then runs `settle` t0 before the window
@@ -85,11 +85,13 @@ def refined_start(Re=2.0e4, C_coarse=0.13, t_start=200, log=print):
             log_(f"coarse LES {Nc}^3: {coarse.steps} of {steps_c} steps, {time.time() - tic:.0f} s")
         rho_c, u_c = coarse.moments()
         coarse.close()
+        if not (np.isfinite(u_c).all() and np.isfinite(rho_c).all()):
+            raise RuntimeError(f"the coarse {Nc}^3 run (C = {C_coarse}) became non-finite")
         del coarse
         torch.cuda.empty_cache()
         u = np.stack([spectral_upsample(u_c[a], N) for a in range(3)])
         rho = spectral_upsample(rho_c, N)
-        log_(f"interpolated {Nc}^3 -> {N}^3, {time.time() - tic:.0f} s")
+        log_(f"interpolated {Nc}^3 (C = {C_coarse}) -> {N}^3, {time.time() - tic:.0f} s")
         lat.init_velocity(torch.from_numpy(u).cuda(), torch.from_numpy(rho).cuda())
         return t_start * T0
     return start
@@ -186,7 +188,8 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
 
 
 def run(scale=2, t_start=200, t_end=300, every=1000,
-        log=lambda m: print(m, file=sys.stderr, flush=True), refine=False, settle=5):
+        log=lambda m: print(m, file=sys.stderr, flush=True), refine=False, settle=5,
+        coarse_C=0.13):
     """scale = 800 / N_DNS: 1 is the paper's pair (800^3 / 100^3), 2 is 400^3 / 50^3.
     refine: the paper's pair, the DNS from the interpolated developed flow of a
     coarser LES at t/t0 = t_start and averaged over [t_start + settle, t_end]."""
@@ -200,14 +203,15 @@ def run(scale=2, t_start=200, t_end=300, every=1000,
     w0 = t_start + settle if refine else t_start
     les = one_run("les", N_les, tau_les, 0.13, w0, t_end, every, log)
     dns = one_run("dns", N_dns, tau_dns, 0.0, w0, t_end, every, log,
-                  start=refined_start(Re, 0.13, t_start, log) if refine else None)
+                  start=refined_start(Re, coarse_C, t_start, log) if refine else None)
     t_start = w0
     # the LES spectrum on the DNS's k eta grid (Kolmogorov units, log interpolation)
     kd, Ed = np.array(dns["k_eta"]), np.array(dns["E_kolmogorov"])
     kl, El = np.array(les["k_eta"]), np.array(les["E_kolmogorov"])
     m = (kd >= kl[0]) & (kd <= kl[-1])
     ratio = np.exp(np.interp(np.log(kd[m]), np.log(kl), np.log(El)) - np.log(Ed[m]))
-    return dict(scale=scale, Re=Re, window=[t_start, t_end], refined=refine, les=les, dns=dns,
+    return dict(scale=scale, Re=Re, window=[t_start, t_end], refined=refine,
+                coarse_C=coarse_C if refine else None, les=les, dns=dns,
                 les_over_dns_spectrum=dict(k_eta=[float(v) for v in kd[m]],
                                            ratio=[float(v) for v in ratio]))
 
@@ -222,9 +226,11 @@ def main():
                     help="800^3 / 100^3 with the DNS started from an interpolated coarse LES")
     ap.add_argument("--settle", type=int, default=5,
                     help="t0 between the refined start and the window")
+    ap.add_argument("--coarse-C", type=float, default=0.13,
+                    help="Smagorinsky C of the coarse run of the refined start (0: DNS)")
     a = ap.parse_args()
     print(json.dumps(run(a.scale, a.t_start, a.t_end, a.every, refine=a.refine,
-                         settle=a.settle)), flush=True)
+                         settle=a.settle, coarse_C=a.coarse_C)), flush=True)
 
 
 if __name__ == "__main__":
