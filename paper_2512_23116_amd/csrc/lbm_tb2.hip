@@ -26,8 +26,8 @@
 // Per cell the arithmetic is the single-step collision, and for 16-bit
 // storage the LDS buffers hold the intermediate level in the storage format:
 // the result is that of two single steps up to the rounding of the FP32
-// collision (the compilers of the two kernels may fuse its multiply-adds
-// differently).  It does not depend on the work plan.
+// collision (the compiler may fuse the collision's multiply-adds differently
+// in the two kernels).  It does not depend on the work plan.
 #include <algorithm>
 #include <array>
 #include <atomic>
