@@ -290,7 +290,8 @@ lbm_status lbm_snapshot_end(lbm_handle* h, lbm_stats* stats, double* E, float* k
  *   E[k] = 1/2 sum_{k - 1/2 <= |q| < k + 1/2} |u_hat(q)|^2,  u_hat = FFT(u) / ncells,
  * for integer shells k = 0..kmax (0 <= kmax <= 4096), u the velocity with the
  * half-force shift of eq. guo_velocity.  FP64 FFT (hipFFT) on the device; the
- * shell sums use LDS atomics, so the last bits may vary between calls.  Host
+ * shell sums run in a fixed order, so a state gives the same spectrum bit for
+ * bit on every call (and through lbm_snapshot_begin/_end).  Host
  * double[kmax+1].  The first call creates the FFT plan and device buffers
  * (~32 bytes per cell plus kmax-sized partial sums) that the handle keeps for
  * later analysis calls until lbm_destroy.
@@ -311,7 +312,7 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
  * central difference of ln E_L over ln k (exact for power laws).  The paper's printed
  * ratio does not equal 1 for isotropic fields; this is the isotropic relation
  * E_22 = (E_11 - k dE_11/dk) / 2, under which IC = 1.  FP64 FFT (hipFFT) on the
- * device, sums with LDS atomics (last bits may vary between calls).  Host
+ * device, sums in a fixed order (bitwise the same on every call).  Host
  * double[9 (kmax+1)] and double[kmax+1].  Shares the analysis buffers and FFT
  * plan of lbm_spectrum.  Synchronises. */
 lbm_status lbm_spectra_1d(lbm_handle* h, int32_t kmax, double* E, double* ic);
