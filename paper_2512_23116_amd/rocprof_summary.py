@@ -13,7 +13,7 @@ with a known-size copy kernel; the counters' reading for it calibrates the
 counters to bytes (FETCH_SIZE reads half of the true bytes on MI355X), and the
 calibrated bytes per step launch are compared with the algorithmic 2*19*b*N^3.
 With ``--traffic-out`` one line per lattice is appended for bench.py:
-``<N>_<precision>_<streaming>[_tb2] <kernel-source sha> <fetch bytes> <write bytes>``,
+``<N>_<precision>_<streaming>[_tb2] <kernel code sha> <fetch bytes> <write bytes>``,
 the sha taken over that kernel family's gfx950 machine code in the built library
 (kernel_code_sha).
 With ``--durations-out`` the trace's mean duration per step launch is written
