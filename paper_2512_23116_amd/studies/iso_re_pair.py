@@ -97,7 +97,7 @@ def refined_start(Re=2.0e4, C_coarse=0.13, t_start=200, log=print):
     return start
 
 
-def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
+def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None, precision="fp32"):
     """A run to t_end, averaged over [t_start, t_end]: from the Taylor-Green start,
     or from start(lattice), which initialises the lattice and returns the step
     count its state stands for (at most t_start t0: the run steps on from there
@@ -108,7 +108,7 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
     stream = torch.cuda.Stream()
     tb = 2 if kind == "dns" else 0
     lat = lbm.Lattice((N, N, N), tau0, C, paper_modes(params.forcing_amplitude(N)),
-                      precision="fp32", streaming="ab" if tb else "aa", smag_form=1,
+                      precision=precision, streaming="ab" if tb else "aa", smag_form=1,
                       steps_per_graph=64, temporal_block=tb, stream=stream)
     if start is None:
         lat.init(lbm.LBM_INIT_TGV3D, params.U0)
@@ -138,6 +138,9 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
         tb_ = lat.turbulence()
         tb_["t"] = step / t0
         scales.append(tb_)
+        log(f"{kind} {N}^3 snapshot t/t0 = {step / t0:g}: resolved dissipation / injection "
+            f"{tb_['eps_spec'] / tb_['injection'] if tb_['injection'] else float('nan'):.3f}, "
+            f"Re_lambda {tb_['re_lambda']:.1f}")
         if C > 0:
             st = lat.stats()
             th.append((st["theta_mean"], st["theta_var"], st["theta_min"], st["theta_max"]))
@@ -157,7 +160,7 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
     eta = (nu0 ** 3 / eps) ** 0.25
     k = np.arange(kmax + 1)
     kap = 2 * np.pi * k / N
-    out = dict(kind=kind, N=N, tau0=tau0, C=C, Re=0.043 * N / nu0, snapshots=n,
+    out = dict(kind=kind, N=N, tau0=tau0, C=C, Re=0.043 * N / nu0, snapshots=n, precision=precision,
                eps=eps, eps_spec=float(np.mean([s["eps_spec"] for s in scales])),
                eps_strain_plus_sgs=float(np.mean([s["eps_strain"] + s["eps_sgs"] for s in scales])),
                eta=eta, re_lambda=float(np.mean([s["re_lambda"] for s in scales])),
@@ -189,7 +192,7 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None):
 
 def run(scale=2, t_start=200, t_end=300, every=1000,
         log=lambda m: print(m, file=sys.stderr, flush=True), refine=False, settle=5,
-        coarse_C=0.13):
+        coarse_C=0.13, dns_precision="fp32"):
     """scale = 800 / N_DNS: 1 is the paper's pair (800^3 / 100^3), 2 is 400^3 / 50^3.
     refine: the paper's pair, the DNS from the interpolated developed flow of a
     coarser LES at t/t0 = t_start and averaged over [t_start + settle, t_end]."""
@@ -203,7 +206,8 @@ def run(scale=2, t_start=200, t_end=300, every=1000,
     w0 = t_start + settle if refine else t_start
     les = one_run("les", N_les, tau_les, 0.13, w0, t_end, every, log)
     dns = one_run("dns", N_dns, tau_dns, 0.0, w0, t_end, every, log,
-                  start=refined_start(Re, coarse_C, t_start, log) if refine else None)
+                  start=refined_start(Re, coarse_C, t_start, log) if refine else None,
+                  precision=dns_precision)
     t_start = w0
     # the LES spectrum on the DNS's k eta grid (Kolmogorov units, log interpolation)
     kd, Ed = np.array(dns["k_eta"]), np.array(dns["E_kolmogorov"])
@@ -228,9 +232,12 @@ def main():
                     help="t0 between the refined start and the window")
     ap.add_argument("--coarse-C", type=float, default=0.13,
                     help="Smagorinsky C of the coarse run of the refined start (0: DNS)")
+    ap.add_argument("--dns-precision", default="fp32", choices=("fp32", "fp16", "bf16"),
+                    help="storage of the DNS populations (two steps per pass)")
     a = ap.parse_args()
     print(json.dumps(run(a.scale, a.t_start, a.t_end, a.every, refine=a.refine,
-                         settle=a.settle, coarse_C=a.coarse_C)), flush=True)
+                         settle=a.settle, coarse_C=a.coarse_C,
+                         dns_precision=a.dns_precision)), flush=True)
 
 
 if __name__ == "__main__":
