@@ -163,3 +163,17 @@ def test_refined_start_carries_the_coarse_flow_onto_the_fine_lattice():
     assert np.isfinite(fine.populations()).all()
     fine.close()
     torch.cuda.empty_cache()
+
+
+def test_one_run_from_a_start_hook_counts_steps_from_the_hooks_time():
+    """one_run with the refined start on a small lattice: the state stands for
+    t_start t0 steps, so the window's snapshots fall at t_start, t_start + 1/2 and
+    t_end without stepping the lattice from 0 again."""
+    from paper_2512_23116_amd import params
+    from paper_2512_23116_amd.studies import iso_re_pair as P
+    N, Re = 32, 2.0e3
+    out = P.one_run("dns", N, params.tau0_from_re(N, Re), 0.0, 2, 3, 500, lambda m: None,
+                    start=P.refined_start(Re, 0.13, 2, log=lambda m: None))
+    assert out["snapshots"] == 3
+    assert [s[0] for s in out["series"]] == [2.0, 2.5, 3.0]
+    assert all(math.isfinite(s[2]) for s in out["series"])
