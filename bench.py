@@ -493,6 +493,9 @@ def main():
                 "roofline": {"bound": "hbm", "achieved": round(rr["achieved"], 1),
                              "peak": rr["peak"], "unit": "GB/s", "frac": round(rr["frac"], 4),
                              "traffic": counter_traffic(f"{args.large_N}_{prec}_aa"),
+                             "avg_launch_us": round(pr["avg_launch_us"], 2),
+                             "profile_avg_launch_us":
+                                 profile_launch_us(f"{args.large_N}_{prec}_aa"),
                              "pattern_ceiling": pr["pattern"]},
                 "vs_fp32": precision_errors(pr, large, args.large_N)}
             log(f"precision: {prec} {pr['mlups']:.0f} MLUPS, {rr['frac']:.3f} of HBM peak, "
@@ -513,7 +516,9 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(own, 1), "peak": rr["peak"],
                          "unit": "GB/s", "frac": round(own / rr["peak"], 4),
                          "traffic": counter_traffic(f"{args.large_N}_fp16_ab_tb2", "k_step_tb2"),
-                         "avg_launch_us": round(pass_us, 3)},
+                         "avg_launch_us": round(pass_us, 3),
+                         "profile_avg_launch_us":
+                             profile_launch_us(f"{args.large_N}_fp16_ab_tb2", "k_step_tb2")},
             "step_equivalent": {"achieved": round(rr["achieved"], 1), "frac": round(rr["frac"], 4)},
             "vs_fp32": precision_errors(pr, large, args.large_N)}
         log(f"precision: fp16 two steps per pass {pr['mlups']:.0f} MLUPS, "
@@ -617,6 +622,9 @@ def main():
                                         "peak": lr["peak"], "unit": "GB/s",
                                         "frac": round(lr["frac"], 4),
                                         "traffic": counter_traffic(f"{args.large_N}_fp32_ab"),
+                                        "avg_launch_us": round(large_ab["avg_launch_us"], 2),
+                                        "profile_avg_launch_us":
+                                            profile_launch_us(f"{args.large_N}_fp32_ab"),
                                         "pattern_ceiling": large_ab["pattern"]}}
     if large_tb2:
         lr = large_tb2["roofline"]
@@ -632,7 +640,9 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(own, 1), "peak": lr["peak"],
                          "unit": "GB/s", "frac": round(own / lr["peak"], 4),
                          "traffic": counter_traffic(f"{args.large_N}_fp32_ab_tb2", "k_step_tb2"),
-                         "avg_launch_us": round(pass_us, 3)},
+                         "avg_launch_us": round(pass_us, 3),
+                         "profile_avg_launch_us":
+                             profile_launch_us(f"{args.large_N}_fp32_ab_tb2", "k_step_tb2")},
             "step_equivalent": {
                 "achieved": round(lr["achieved"], 1), "frac": round(lr["frac"], 4),
                 "note": "2*19*4 B per cell update / time: the bytes a one-step-per-pass "
