@@ -28,6 +28,7 @@ K_t-statistics and spectral errors against the FP32 run, the batched-serving run
 on the host cores on a bounded sample.
 """
 import argparse
+import gc
 import json
 import os
 import statistics
@@ -145,24 +146,35 @@ def run_workload(lbm, params, N, precision, streaming, intervals, warmup, repeat
     lat.sync()
     torch.cuda.synchronize()
     reps, last = [], None
+    # The host runs one interval ahead of the device: a pause of the cyclic
+    # garbage collector longer than an interval (a full pass over torch's objects
+    # takes tens of ms) would leave the device idle.  It is run before each
+    # repeat and kept off inside it, as timeit does.
+    gc_was_enabled = gc.isenabled()
     for _ in range(repeats):
         events = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(intervals):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            lat.step(interval)
-            e1.record(stream)
-            events.append((e0, e1))
-            if i > 0:
-                last = lat.snapshot_end()
-            lat.snapshot_begin(kmax, zmid)
-        last = lat.snapshot_end()
-        lat.sync()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(intervals):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                lat.step(interval)
+                e1.record(stream)
+                events.append((e0, e1))
+                if i > 0:
+                    last = lat.snapshot_end()
+                lat.snapshot_begin(kmax, zmid)
+            last = lat.snapshot_end()
+            lat.sync()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            if gc_was_enabled:
+                gc.enable()
         kern_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
         cells = N ** 3 * intervals * interval
         reps.append(dict(wall_s=wall, mlups=cells / wall / 1e6,
