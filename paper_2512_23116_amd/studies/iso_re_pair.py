@@ -31,6 +31,7 @@ theta = tau_e - 1/2 (Sec. 5.1).
 
     python -m paper_2512_23116_amd.studies.iso_re_pair [--scale 2] [--t-end 300]
     python -m paper_2512_23116_amd.studies.iso_re_pair --refine [--t-start 200 --settle 5 --t-end 220]
+    python -m paper_2512_23116_amd.studies.iso_re_pair --scale 1 --les-only --t-end 1000
 """
 import argparse
 import json
@@ -192,10 +193,12 @@ def one_run(kind, N, tau0, C, t_start, t_end, every, log, start=None, precision=
 
 def run(scale=2, t_start=200, t_end=300, every=1000,
         log=lambda m: print(m, file=sys.stderr, flush=True), refine=False, settle=5,
-        coarse_C=0.13, dns_precision="fp32"):
+        coarse_C=0.13, dns_precision="fp32", les_only=False):
     """scale = 800 / N_DNS: 1 is the paper's pair (800^3 / 100^3), 2 is 400^3 / 50^3.
     refine: the paper's pair, the DNS from the interpolated developed flow of a
-    coarser LES at t/t0 = t_start and averaged over [t_start + settle, t_end]."""
+    coarser LES at t/t0 = t_start and averaged over [t_start + settle, t_end].
+    les_only: the LES of the pair alone, from the Taylor-Green start, averaged
+    over [t_start, t_end] (its window can then be the paper's whole [200, 1000])."""
     from .. import params
     if refine:
         scale = 1
@@ -203,6 +206,9 @@ def run(scale=2, t_start=200, t_end=300, every=1000,
     Re = 2.0e4 / scale
     tau_dns = params.tau0_from_re(N_dns, Re)       # 0.5 + 5.16e-3 for any scale
     tau_les = params.tau0_from_re(N_les, Re)       # 0.5 + 6.45e-4
+    if les_only:
+        les = one_run("les", N_les, tau_les, 0.13, t_start, t_end, every, log)
+        return dict(scale=scale, Re=Re, window=[t_start, t_end], les=les)
     w0 = t_start + settle if refine else t_start
     les = one_run("les", N_les, tau_les, 0.13, w0, t_end, every, log)
     dns = one_run("dns", N_dns, tau_dns, 0.0, w0, t_end, every, log,
@@ -234,10 +240,12 @@ def main():
                     help="Smagorinsky C of the coarse run of the refined start (0: DNS)")
     ap.add_argument("--dns-precision", default="fp32", choices=("fp32", "fp16", "bf16"),
                     help="storage of the DNS populations (two steps per pass)")
+    ap.add_argument("--les-only", action="store_true",
+                    help="run the LES of the pair alone over [t-start, t-end]")
     a = ap.parse_args()
     print(json.dumps(run(a.scale, a.t_start, a.t_end, a.every, refine=a.refine,
                          settle=a.settle, coarse_C=a.coarse_C,
-                         dns_precision=a.dns_precision)), flush=True)
+                         dns_precision=a.dns_precision, les_only=a.les_only)), flush=True)
 
 
 if __name__ == "__main__":

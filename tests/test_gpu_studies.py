@@ -112,6 +112,12 @@ def test_iso_re_pair_study_small():
         assert all(math.isfinite(v) and v > 0 for v in r["E_kolmogorov"])
         assert all(math.isfinite(v) for v in r["F4"])
     assert res["les"]["theta_min"] > 0
+    # the LES alone gives the same record (deterministic), and no DNS
+    alone = iso_re_pair.run(scale=16, t_start=2, t_end=3, every=500, log=lambda m: None,
+                            les_only=True)
+    assert "dns" not in alone and alone["window"] == [2, 3]
+    assert alone["les"]["E_kolmogorov"] == res["les"]["E_kolmogorov"]
+    assert alone["les"]["theta_mean"] == res["les"]["theta_mean"]
 
 
 def test_c_sweep_study_small():
