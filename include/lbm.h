@@ -293,8 +293,10 @@ lbm_status lbm_snapshot_end(lbm_handle* h, lbm_stats* stats, double* E, float* k
  * shell sums run in a fixed order, so a state gives the same spectrum bit for
  * bit on every call (and through lbm_snapshot_begin/_end).  Host
  * double[kmax+1].  The first call creates the FFT plan and device buffers
- * (~32 bytes per cell plus kmax-sized partial sums) that the handle keeps for
- * later analysis calls until lbm_destroy.
+ * (~32 bytes per cell, ~48 for lattices of up to 2^24 cells, whose three
+ * velocity components are transformed in one batched call; plus kmax-sized
+ * partial sums) that the handle keeps for later analysis calls until
+ * lbm_destroy.
  * Synchronises. */
 lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E);
 

@@ -256,6 +256,8 @@ struct AnalysisCache {
     size_t out_elems = 0;
     hipfftHandle plan = nullptr;
     bool has_plan = false;
+    hipfftHandle plan3 = nullptr;         // the three components in one batched call
+    bool has_plan3 = false;
     // snapshot (lbm_snapshot_begin / _end): completion event, the device K_t
     // plane and the page-locked results
     hipEvent_t ev_snap = nullptr;
@@ -280,6 +282,7 @@ void release_analysis(AnalysisCache* a) {
     if (a->h_E) (void)hipHostFree(a->h_E);
     if (a->h_plane) (void)hipHostFree(a->h_plane);
     if (a->has_plan) (void)hipfftDestroy(a->plan);
+    if (a->has_plan3) (void)hipfftDestroy(a->plan3);
     if (a->hist) (void)hipFree(a->hist);
     if (a->u) (void)hipFree(a->u);
     if (a->c) (void)hipFree(a->c);
@@ -345,6 +348,75 @@ lbm_status fft_plan(lbm_handle* h, AnalysisCache& a, hipStream_t stream) {
     return LBM_OK;
 }
 
+// Lattices of up to 2^24 cells (256^3) transform the three velocity components in
+// one batched call: at those sizes each transform's kernels are short and
+// latency-bound, and batching them costs 16 bytes per cell more for the
+// three-component transform buffer.  Larger lattices transform one component
+// at a time into a one-component buffer, where the kernels are bandwidth-bound
+// and the memory counts.
+bool batched_fft(const lbm_handle* h) { return h->args.ncell <= (size_t(1) << 24); }
+
+lbm_status fft_plan3(lbm_handle* h, AnalysisCache& a, hipStream_t stream) {
+    if (!a.has_plan3) {
+        const int nx = (int)h->args.nx, ny = (int)h->args.ny, nz = (int)h->args.nz;
+        int n[3] = {nz, ny, nx}, inembed[3] = {nz, ny, nx}, onembed[3] = {nz, ny, nx / 2 + 1};
+        const int idist = nz * ny * nx, odist = nz * ny * (nx / 2 + 1);
+        hipfftResult fr = hipfftPlanMany(&a.plan3, 3, n, inembed, 1, idist, onembed, 1, odist,
+                                         HIPFFT_D2Z, 3);
+        if (fr != HIPFFT_SUCCESS)
+            return set_err(h, LBM_ERR_DEVICE, std::string("hipfftPlanMany: ") + fft_error(fr));
+        a.has_plan3 = true;
+    }
+    hipfftResult fr = hipfftSetStream(a.plan3, stream);
+    if (fr != HIPFFT_SUCCESS)
+        return set_err(h, LBM_ERR_DEVICE, std::string("hipfftSetStream: ") + fft_error(fr));
+    return LBM_OK;
+}
+
+// Enqueue on `stream` the shell spectrum E[0..kmax] of the velocity u ([3][ncell])
+// into a.out: the transforms, the per-block shell sums of each component and
+// their fixed-order reduction.  a.c, a.part and a.out must be allocated
+// (spectrum_buffers).
+lbm_status enqueue_spectrum(lbm_handle* h, AnalysisCache& a, const double* u, int kmax,
+                            hipStream_t stream) {
+    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
+    const size_t nc = h->args.ncell, nmodes = (nx / 2 + 1) * (size_t)ny * nz;
+    const bool batched = batched_fft(h);
+    lbm_status st = batched ? fft_plan3(h, a, stream) : fft_plan(h, a, stream);
+    if (st != LBM_OK) return st;
+    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
+    const size_t shm = (size_t)(kmax + 1) * sizeof(double);
+    const int bt = bin_threads(shm);
+    hipfftResult fr = HIPFFT_SUCCESS;
+    if (batched) fr = hipfftExecD2Z(a.plan3, (hipfftDoubleReal*)u, a.c);
+    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
+        const hipfftDoubleComplex* cc = a.c;
+        if (batched) {
+            cc = a.c + (size_t)c * nmodes;
+        } else {
+            fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
+            if (fr != HIPFFT_SUCCESS) break;
+        }
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), stream, cc,
+                           nx, ny, nz, (int)kmax, inv_n2, a.part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, stream,
+                           (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
+    }
+    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(h, e, "spectrum kernels");
+    return LBM_OK;
+}
+
+// The transform buffer and the partial and reduced sums of a spectrum to kmax.
+hipError_t spectrum_buffers(lbm_handle* h, AnalysisCache& a, int kmax) {
+    const size_t nmodes = (h->args.nx / 2 + 1) * (size_t)h->args.ny * h->args.nz;
+    hipError_t e = ensure(a.c, a.c_elems, batched_fft(h) ? 3 * nmodes : nmodes);
+    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
+    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -353,33 +425,16 @@ lbm_status lbm_spectrum(lbm_handle* h, int32_t kmax, double* E) {
     if (!h) return LBM_ERR_INVALID_ARG;
     if (!E || kmax < 0 || kmax > 4096) return set_err(h, LBM_ERR_INVALID_ARG, "kmax must be 0..4096");
     if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
-    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
-    const size_t nc = h->args.ncell, hx = nx / 2 + 1, nmodes = hx * (size_t)ny * nz;
     const double* u = nullptr;
     lbm_status st = velocity(h, &u);
     if (st != LBM_OK) return st;
     AnalysisCache& a = cache(h);
-    hipError_t e = ensure(a.c, a.c_elems, nmodes);
-    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
-    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
+    hipError_t e = spectrum_buffers(h, a, kmax);
     if (e != hipSuccess) return hip_err(h, e, "hipMalloc(spectrum)");
-    st = fft_plan(h, a, h->stream);
+    st = enqueue_spectrum(h, a, u, kmax, h->stream);
     if (st != LBM_OK) return st;
-    hipfftResult fr = HIPFFT_SUCCESS;
-    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
-    const int bt = bin_threads(shm);
-    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
-        fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
-        if (fr != HIPFFT_SUCCESS) break;
-        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), h->stream,
-                           (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
-        hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
-                           (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
-    }
-    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "spectrum");
     return LBM_OK;
@@ -392,14 +447,11 @@ lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z) {
     if (!h->initialized) return set_err(h, LBM_ERR_STATE, "state not initialised");
     AnalysisCache& a = cache(h);
     if (a.snap_pending) return set_err(h, LBM_ERR_STATE, "a snapshot is already pending");
-    const uint32_t nx = h->args.nx, ny = h->args.ny, nz = h->args.nz;
-    const size_t nc = h->args.ncell, nxy = h->args.nxy, nmodes = (nx / 2 + 1) * (size_t)ny * nz;
+    const size_t nc = h->args.ncell, nxy = h->args.nxy;
     // buffers, created on first use and kept until lbm_destroy
     hipError_t e = hipSuccess;
     if (!a.u) e = hipMalloc((void**)&a.u, 3 * nc * sizeof(double));
-    if (e == hipSuccess) e = ensure(a.c, a.c_elems, nmodes);
-    if (e == hipSuccess) e = ensure(a.part, a.part_elems, (size_t)kAnaBlocks * (kmax + 1));
-    if (e == hipSuccess) e = ensure(a.out, a.out_elems, (size_t)(kmax + 1));
+    if (e == hipSuccess) e = spectrum_buffers(h, a, kmax);
     if (e == hipSuccess && !a.d_plane) e = hipMalloc((void**)&a.d_plane, nxy * sizeof(float));
     if (e == hipSuccess && !a.h_sums) e = hipHostMalloc((void**)&a.h_sums, kDiagSlots * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess && !a.h_plane) e = hipHostMalloc((void**)&a.h_plane, nxy * sizeof(float), hipHostMallocDefault);
@@ -412,8 +464,6 @@ lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z) {
     }
     if (e == hipSuccess && !a.ev_snap) e = hipEventCreateWithFlags(&a.ev_snap, hipEventDisableTiming);
     if (e != hipSuccess) return hip_err(h, e, "snapshot buffers");
-    lbm_status st = fft_plan(h, a, h->stream);
-    if (st != LBM_OK) return st;
     // everything on the handle's stream, in order with the steps: the state reads,
     // the transforms of the velocity and the copies to page-locked memory
     double* sums = nullptr;
@@ -427,21 +477,10 @@ lbm_status lbm_snapshot_begin(lbm_handle* h, int32_t kmax, int32_t z) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(a.h_plane, a.d_plane, nxy * sizeof(float), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_err(h, e, "snapshot (state reads)");
-    const double inv_n2 = 1.0 / ((double)nc * (double)nc);
+    lbm_status st = enqueue_spectrum(h, a, a.u, kmax, h->stream);
+    if (st != LBM_OK) return st;
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
-    const int bt = bin_threads(shm);
-    hipfftResult fr = HIPFFT_SUCCESS;
-    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
-        fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(a.u + (size_t)c * nc), a.c);
-        if (fr != HIPFFT_SUCCESS) break;
-        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), h->stream,
-                           (const hipfftDoubleComplex*)a.c, nx, ny, nz, (int)kmax, inv_n2, a.part);
-        hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, h->stream,
-                           (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
-    }
-    if (fr != HIPFFT_SUCCESS) return set_err(h, LBM_ERR_DEVICE, std::string("hipFFT: ") + fft_error(fr));
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(a.h_E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(a.h_E, a.out, shm, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipEventRecord(a.ev_snap, h->stream);
     if (e != hipSuccess) return hip_err(h, e, "snapshot (spectrum)");
     a.snap_pending = true;
