@@ -29,14 +29,16 @@ constexpr int kAnaBlocks = 1024;
 // partial sums in block order).  A block has 1 to 4 waves, as many as let their
 // histograms fit 64 KB of LDS.
 
-// Per-block partial sums of 1/2 w |c|^2 / n^2 over the shells 0..kmax; w = 2 for
-// the kx > 0 modes that stand for a conjugate pair.  Along a row the shell index
+// Per-block partial sums of 1/2 w |c|^2 / n^2 over the shells 0..kmax, |c|^2
+// summed over ncomp transforms stored cstride apart (the velocity components);
+// w = 2 for the kx > 0 modes that stand for a conjugate pair.  Along a row the shell index
 // never decreases with kx, so equal shells are contiguous runs of lanes: a
 // segmented scan over the 64 lanes sums each run, and the run's last lane adds
 // that sum to the wave's histogram (one lane per shell, no two lanes on one bin).
-__global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c, uint32_t nx,
-                                                   uint32_t ny, uint32_t nz, int kmax,
-                                                   double inv_n2, double* partials) {
+__global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c, uint64_t cstride,
+                                                   int ncomp, uint32_t nx, uint32_t ny,
+                                                   uint32_t nz, int kmax, double inv_n2,
+                                                   double* partials) {
     extern __shared__ double hist[];   // [waves][kmax + 1]
     const int nb = kmax + 1, waves = (int)(blockDim.x >> 6);
     for (int k = threadIdx.x; k < waves * nb; k += blockDim.x) hist[k] = 0.0;
@@ -62,8 +64,12 @@ __global__ __launch_bounds__(256) void k_shell_bin(const hipfftDoubleComplex* c,
             double v = 0.0;
             if (in && shell <= kmax) {
                 const double w = (ix == 0 || (nx % 2 == 0 && ix == nx / 2)) ? 1.0 : 2.0;
-                const hipfftDoubleComplex z = crow[ix];
-                v = 0.5 * w * (z.x * z.x + z.y * z.y) * inv_n2;
+                double e = 0.0;   // |u_hat|^2 summed over the ncomp components
+                for (int q = 0; q < ncomp; ++q) {
+                    const hipfftDoubleComplex z = crow[(uint64_t)q * cstride + ix];
+                    e += z.x * z.x + z.y * z.y;
+                }
+                v = 0.5 * w * e * inv_n2;
             }
             for (int d = 1; d < 64; d <<= 1) {   // segmented inclusive scan over the runs
                 const double vu = __shfl_up(v, d, 64);
@@ -388,17 +394,18 @@ lbm_status enqueue_spectrum(lbm_handle* h, AnalysisCache& a, const double* u, in
     const size_t shm = (size_t)(kmax + 1) * sizeof(double);
     const int bt = bin_threads(shm);
     hipfftResult fr = HIPFFT_SUCCESS;
+    // batched: one binning pass sums the three components mode by mode;
+    // otherwise each component's transform is binned and added in turn
+    const int passes = batched ? 1 : 3, ncomp = batched ? 3 : 1;
     if (batched) fr = hipfftExecD2Z(a.plan3, (hipfftDoubleReal*)u, a.c);
-    for (int c = 0; c < 3 && fr == HIPFFT_SUCCESS; ++c) {
-        const hipfftDoubleComplex* cc = a.c;
-        if (batched) {
-            cc = a.c + (size_t)c * nmodes;
-        } else {
+    for (int c = 0; c < passes && fr == HIPFFT_SUCCESS; ++c) {
+        if (!batched) {
             fr = hipfftExecD2Z(a.plan, (hipfftDoubleReal*)(u + (size_t)c * nc), a.c);
             if (fr != HIPFFT_SUCCESS) break;
         }
-        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), stream, cc,
-                           nx, ny, nz, (int)kmax, inv_n2, a.part);
+        hipLaunchKernelGGL(k_shell_bin, dim3(kAnaBlocks), dim3(bt), shm * (bt / 64), stream,
+                           (const hipfftDoubleComplex*)a.c, (uint64_t)nmodes, ncomp, nx, ny, nz,
+                           (int)kmax, inv_n2, a.part);
         hipLaunchKernelGGL(k_sum_rows, dim3(kmax + 1), dim3(256), 0, stream,
                            (const double*)a.part, kAnaBlocks, (int)(kmax + 1), 1.0, c > 0, a.out);
     }
