@@ -174,7 +174,13 @@ lbm_status capture_graph(lbm_handle* h) {
         }
     }
     HIPCHK(h, hipStreamEndCapture(h->cap_stream, &h->graph));
-    HIPCHK(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    const hipError_t e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {   // no half-made graph is kept: the next call captures anew
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+        h->gexec = nullptr;
+        return hip_fail(h, e, "hipGraphInstantiate");
+    }
     return LBM_OK;
 }
 

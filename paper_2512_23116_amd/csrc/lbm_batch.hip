@@ -133,7 +133,13 @@ lbm_status capture(lbm_batch* b) {
         }
     }
     BCHK(b, hipStreamEndCapture(b->cap_stream, &b->graph));
-    BCHK(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    const hipError_t e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {   // no half-made graph is kept: the next call captures anew
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        b->gexec = nullptr;
+        return bhip(b, e, "hipGraphInstantiate");
+    }
     return LBM_OK;
 }
 
