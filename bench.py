@@ -2,11 +2,14 @@
 """Benchmark of the D3Q19 MRT-Smagorinsky LES hot path on one MI355X.
 
 Prints ONE JSON line.  The headline workload is forced-HIT LES on a 100^3
-periodic lattice in FP32 with in-place AA streaming (Re = 2e4 at U0 = 0.043,
-C_s = 0.1 in nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with
-seeded phases, 1e-3 noise start) with its diagnostics every 500 lattice steps:
-the K_t / theta statistics, the K_t map of the mid-z plane (copied to the host)
-and the energy spectrum E(k), k <= N/2.
+periodic lattice in FP32 (Re = 2e4 at U0 = 0.043, C_s = 0.1 in
+nu_t = (C_s Delta)^2 |S|, solenoidal forcing on |k| <= 2 with seeded phases,
+1e-3 noise start) with its diagnostics every 500 lattice steps: the K_t / theta
+statistics, the K_t map of the mid-z plane (copied to the host) and the energy
+spectrum E(k), k <= N/2.  It streams A/B (two arrays): the 2 x 76 MB stay in the
+last-level cache, where the step runs about 2 % faster than in place
+(--streaming aa).  The 800^3 lines keep the in-place AA form, whose 39 GB
+state is half of A/B's.
 
 A bench "step" is one pass of the whole hot path over the workload: one
 snapshot interval, i.e. 500 lattice time steps (one replay of a captured graph
@@ -406,7 +409,8 @@ def main():
     ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--N", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
-    ap.add_argument("--streaming", default="aa", choices=["aa", "ab"])
+    ap.add_argument("--streaming", default="ab", choices=["aa", "ab"],
+                    help="streaming of the headline lattice (A/B: two arrays; AA: in place)")
     ap.add_argument("--diag-every", type=int, default=500,
                     help="lattice steps per snapshot interval (one captured graph)")
     ap.add_argument("--steps-per-graph", type=int, default=500,
@@ -573,7 +577,9 @@ def main():
         "config": {
             "workload": (f"forced HIT LES {args.N}^3 periodic, D3Q19 MRT-Smagorinsky C_s=0.1 "
                          f"(tau0={main_run['tau0']:.6f}, Re=2e4, U0=0.043), "
-                         f"{args.precision} {args.streaming.upper()} storage, 16-mode |k|<=2 "
+                         f"{args.precision} storage, "
+                         f"{'A/B (two-array)' if args.streaming == 'ab' else 'AA (in-place)'} "
+                         f"streaming, 16-mode |k|<=2 "
                          f"forcing, 1e-3 noise start; one step = {args.diag_every} lattice "
                          f"steps (one graph replay) + K_t/theta statistics + K_t map of the "
                          f"mid-z plane to host + energy spectrum E(k<={args.N // 2}) "

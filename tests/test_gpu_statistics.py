@@ -1,7 +1,8 @@
 """Long forced-HIT LES on the GPU against the FP64 oracle's statistics.
 
-The workload is the benchmark's: 100^3 periodic, FP32 populations with AA
-streaming, Re = 2e4 at U0 = 0.043, nu_t = (C_s Delta)^2 |S| with C_s = 0.1,
+The workload is the benchmark's: 100^3 periodic, FP32 populations (here with
+AA streaming; the benchmark streams A/B, which gives the same populations bit
+for bit), Re = 2e4 at U0 = 0.043, nu_t = (C_s Delta)^2 |S| with C_s = 0.1,
 16-mode solenoidal forcing on |k| <= 2, 1e-3 noise start, 20000 steps, with the
 domain statistics of theta = tau_e - 1/2 and K_t (Sec. 5.1), the kinetic energy
 and the shell spectrum E(k) (Sec. 2.2) taken every 500 steps on the device.
