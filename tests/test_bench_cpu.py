@@ -88,3 +88,31 @@ def test_kernel_code_sha_follows_the_kernel_machine_code(tmp_path, monkeypatch):
     lib2 = flipped(off + size // 2)
     assert {f: R.kernel_code_sha(f, lib2) for f in ("k_step", "k_step_tb2")} == \
         {f: base[f] for f in ("k_step", "k_step_tb2")}
+
+
+def test_profile_rows_are_keyed_by_lattice_pattern_and_storage():
+    """The profile summary names each step launch by its lattice: edge from the
+    grid, AA (patterns 0, 1) or A/B (pattern 2), storage from the codec."""
+    sys.path.insert(0, ROOT)
+    from paper_2512_23116_amd.rocprof_summary import lattice_key
+    assert lattice_key("k_step<CdF32, 2, 0>(LatticeArgs)", 1000192, "fp32", 800) == \
+        ("k_step", "100_fp32_ab")
+    assert lattice_key("k_step<CdF32, 1, 0>(LatticeArgs)", 1000192, "fp32", 800) == \
+        ("k_step", "100_fp32_aa")
+    assert lattice_key("k_step<CdF16, 0, 0>(LatticeArgs)", 512000000, "fp32", 800) == \
+        ("k_step", "800_fp16_aa")
+    assert lattice_key("k_step_tb2<CdBF16, 16>(TB2Args)", 3178496, "fp32", 800) == \
+        ("k_step_tb2", "800_bf16_ab_tb2")
+    assert lattice_key("k_moments<CdF32, 0>(LatticeArgs, double*, double*)", 1000192, "fp32",
+                       800) is None
+
+
+def test_the_committed_profiles_cover_the_default_headline():
+    """The default headline lattice (100^3 FP32 A/B) has a row in the committed
+    trace table and in the counter table; whether it is current is the code
+    sha's business (bench.py prints null for a stale row)."""
+    for table in ("durations_step_kernels_forced_hit_100_800.txt",
+                  "hbm_traffic_step_kernels_forced_hit_100_800.txt"):
+        keys = [l.split()[0] for l in open(os.path.join(ROOT, "profiles", table))
+                if l.strip() and not l.startswith("#")]
+        assert "100_fp32_ab" in keys, table
